@@ -1,0 +1,167 @@
+/*
+ * phylograd -- log-likelihood and all branch-length gradients of a
+ * phylogenetic CTMC model on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Ji et al., "Gradients do grow on trees: a linear-time
+ * O(N)-dimensional gradient for statistical phylogenetics".
+ *   - post-order pruning pass, Section 2.3, Eqs. (postOrderPartialUpdate)
+ *     and (rootInnerProduct);
+ *   - pre-order pass, Section 2.4, Eq. (preOrderUpdate);
+ *   - per-branch derivative, Section 2.5, Eq. (singleRateCaseGradient), with
+ *     rate categories, Section 2.6, Eqs. (discreteRateLikelihood) and
+ *     (GradientWithGamma);
+ *   - diagonal of the Hessian, Section 2.7, Eq. (Hessian).
+ *
+ * Conventions (Section 2.1, made 0-based):
+ *   - N tips are nodes 0..N-1, internal nodes N..2N-2, the root is 2N-2;
+ *   - a branch is named by its child node: branch b (0 <= b < 2N-2) joins
+ *     node b to parent[b]; t[b] is its length;
+ *   - Q[x*m + y] is the rate from parent state x to child state y
+ *     (row-major, off-diagonals >= 0, rows sum to 0); the transition matrix
+ *     of branch b in rate category l is exp(Q * rate[l] * t[b]);
+ *   - the root distribution need not be the stationary one and Q need not be
+ *     reversible;
+ *   - tip observations are bit masks, bit x set = state x allowed (a
+ *     one-hot mask is an observed state, all bits set is missing data,
+ *     Section 2.1's modified tip vector for partial observation);
+ *   - logL = sum_s w_s log L_s over site patterns s with weights w_s >= 0.
+ *
+ * Every function returns PG_OK (0) or a negative PG_E_* code, never
+ * throws and never aborts; pg_last_error() describes the last failure.
+ * All inputs are copied: the caller may free them when a call returns.
+ * Outputs are caller-allocated.  A context is not thread-safe; distinct
+ * contexts are independent.  All device work of a context runs in order on
+ * one HIP stream (its own, or the one given by pg_set_stream).
+ */
+#ifndef PHYLOGRAD_H
+#define PHYLOGRAD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define PG_OK             0
+#define PG_E_INVALID     -1  /* bad argument: NULL pointer, bad size, t not finite or < 0 */
+#define PG_E_TREE        -2  /* not a rooted binary tree in the numbering above        */
+#define PG_E_MODEL       -3  /* Q, root frequencies or rate categories malformed       */
+#define PG_E_PATTERNS    -4  /* empty mask, state beyond m, weight < 0 or not finite   */
+#define PG_E_STATE       -5  /* call order: tree, patterns and model not all set       */
+#define PG_E_OOM         -6  /* device allocation failed                               */
+#define PG_E_DEVICE      -7  /* HIP runtime error or no usable gfx950 device           */
+#define PG_E_ZERO_LIK    -8  /* some pattern with w_s > 0 has likelihood 0: logL=-inf  */
+#define PG_E_UNSUPPORTED -9  /* state count or precision without a compiled kernel     */
+
+/* ---- precisions ------------------------------------------------------ */
+/* PG_FP64: partial vectors, transition matrices and arithmetic in FP64.
+ * PG_FP32: partial vectors and their arithmetic in FP32; the transition
+ *          matrices are computed in FP64 and rounded once; the per-pattern
+ *          scale exponents, the site-weighted sums of logL and of the
+ *          gradient stay in FP64. */
+#define PG_FP64 0
+#define PG_FP32 1
+
+/* ---- kernels reported by pg_get_timing ------------------------------- */
+#define PG_K_PMAT  0  /* transition matrices exp(Q rate t)         */
+#define PG_K_POST  1  /* post-order pass, rescaling, root values   */
+#define PG_K_ROOT  2  /* per-pattern likelihood, logL reduction    */
+#define PG_K_PRE   3  /* pre-order pass fused with the gradient    */
+#define PG_K_GSUM  4  /* fixed-order per-branch gradient reduction */
+#define PG_K_COUNT 5
+
+typedef struct pg_ctx pg_ctx;
+
+/* Create a context on HIP device `device` with precision PG_FP64 or
+ * PG_FP32.  No device memory is allocated until the first evaluation.
+ * Fails with PG_E_DEVICE when the device does not exist or is not gfx950. */
+int pg_create(int device, int precision, pg_ctx** out);
+
+/* Release the context and all its device memory (waits for its stream). */
+void pg_destroy(pg_ctx* ctx);
+
+/* Message for the last failing call on ctx (never NULL; "" if none).
+ * With ctx == NULL, the message of the last failed pg_create. */
+const char* pg_last_error(const pg_ctx* ctx);
+
+/* Run all later device work on `hip_stream` (a hipStream_t, e.g. torch's
+ * current stream); NULL restores the context's own stream.  The caller
+ * keeps ownership of the stream and must keep it alive. */
+int pg_set_stream(pg_ctx* ctx, void* hip_stream);
+
+/* Tree topology (Section 2.1).  parent[2N-1]: parent[v] for every node,
+ * parent[2N-2] == -1 for the root; every internal node has exactly two
+ * children and every node reaches the root.  N >= 2.  Changing N drops the
+ * patterns. Errors: PG_E_INVALID (NULL, N < 2), PG_E_TREE. */
+int pg_set_tree(pg_ctx* ctx, int32_t n_tips, const int32_t* parent);
+
+/* Site patterns.  tip_masks[N*S]: row v (tip v), column s, bit x = state x
+ * allowed, 2 <= m <= 64; weights[S] finite and >= 0.  Needs the tree.
+ * Errors: PG_E_STATE (no tree), PG_E_INVALID, PG_E_PATTERNS (empty mask,
+ * a bit >= m, more than 255 - m distinct partial-ambiguity masks). */
+int pg_set_patterns(pg_ctx* ctx, int32_t n_patterns, int32_t n_states,
+                    const uint64_t* tip_masks, const double* weights);
+
+/* Substitution model (Sections 2.1 and 2.6).  Q[m*m] row-major generator,
+ * root_freqs[m] a probability vector, cat_rates[K] >= 0 and
+ * cat_weights[K] a probability vector (the discrete rate categories
+ * gamma_l and Pr(gamma_l)).  Compiled state counts: m = 4 and m = 20.
+ * Errors: PG_E_INVALID, PG_E_MODEL, PG_E_UNSUPPORTED. */
+int pg_set_model(pg_ctx* ctx, int32_t n_states, const double* Q,
+                 const double* root_freqs, int32_t n_cats,
+                 const double* cat_rates, const double* cat_weights);
+
+/* One evaluation from host memory: t[2N-2] branch lengths in, *logL and,
+ * unless grad == NULL, grad[2N-2] = dlogL/dt_b out.  Blocks until done.
+ * Errors: PG_E_STATE, PG_E_INVALID (t), PG_E_ZERO_LIK (*logL = -inf, grad
+ * left unspecified), PG_E_DEVICE, PG_E_OOM. */
+int pg_logL_and_grad(pg_ctx* ctx, const double* t, double* logL, double* grad);
+
+/* Post-order pass only (transition matrices, pruning, root): *logL out.
+ * The partial vectors stay resident on the device for a later pg_grad. */
+int pg_logL(pg_ctx* ctx, const double* t, double* logL);
+
+/* Pre-order pass on the partials left by the last successful pg_logL (or
+ * pg_logL_and_grad): grad[2N-2] out.  PG_E_STATE if there are none or the
+ * tree, patterns or model changed since. */
+int pg_grad(pg_ctx* ctx, double* grad);
+
+/* Diagonal of the Hessian, d2 logL / dt_b^2, Section 2.7 Eq. (Hessian),
+ * on the partials left by the last pg_logL or pg_logL_and_grad.  Also
+ * returns the gradient in grad[2N-2] unless grad == NULL.  Blocks. */
+int pg_hessian_diag(pg_ctx* ctx, double* grad, double* hess);
+
+/* Device-pointer variant: d_t[2N-2] (FP64, device), d_logL[1] and
+ * d_grad[2N-2] (device, d_grad may be NULL) are read and written
+ * asynchronously on the context's stream; pointers must stay valid until
+ * that stream reaches this work.  No host synchronisation.  Branch lengths
+ * are checked on the device: a non-finite or negative t_b, or a zero
+ * likelihood, makes *d_logL NaN or -inf and is reported by the next
+ * pg_status() call. */
+int pg_logL_and_grad_device(pg_ctx* ctx, const double* d_t, double* d_logL,
+                            double* d_grad);
+
+/* Device-side status of the last device-pointer evaluation (waits for the
+ * stream): PG_OK, PG_E_INVALID (bad t) or PG_E_ZERO_LIK. */
+int pg_status(pg_ctx* ctx);
+
+/* Kernel timing.  While enabled, each evaluation records HIP events around
+ * every kernel on the context's stream and waits for them; pg_get_timing
+ * writes, for each PG_K_* kernel, the summed milliseconds into ms[k] and
+ * the number of launches into launches[k] (arrays of PG_K_COUNT entries;
+ * either may be NULL), then resets the sums. */
+int pg_set_timing(pg_ctx* ctx, int enable);
+int pg_get_timing(pg_ctx* ctx, double* ms, int64_t* launches);
+
+/* Device bytes the context holds now (for admission by HBM footprint), and
+ * the bytes it would hold for a problem of the given size. */
+int64_t pg_device_bytes(const pg_ctx* ctx);
+int64_t pg_footprint_bytes(int32_t n_tips, int32_t n_patterns, int32_t n_states,
+                           int32_t n_cats, int precision);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHYLOGRAD_H */

@@ -1,0 +1,687 @@
+// C-ABI of libphylograd: context, input checks, tree schedule, device
+// buffers and the evaluation sequence.  Declarations and the contract of
+// every entry point are in include/phylograd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "pg_internal.h"
+
+using namespace pg;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct pg_ctx {
+    int device = 0;
+    int precision = PG_FP64;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // tree
+    bool tree_set = false;
+    int n_tips = 0;
+    std::vector<int> parent;
+    std::vector<int2> children;
+    std::vector<int> level_off, level_nodes;
+
+    // patterns
+    bool patterns_set = false;
+    int S = 0, S_pad = 0, m_pat = 0;
+    std::vector<uint8_t> codes;               // [N][S_pad]
+    std::vector<unsigned long long> masks;    // [256]
+    std::vector<double> weights;              // [S_pad]
+
+    // model
+    bool model_set = false;
+    int m = 0, K = 0;
+    std::vector<double> Q, Q2, pi, rates, catw;
+    double qnorm = 0.0;
+
+    // device state
+    bool dev_stale = true;        // host inputs changed since the last upload
+    bool have_partials = false;   // post-order pass results resident
+    std::map<std::string, DevBuf> bufs;
+    EvalArgs args{};
+
+    // timing
+    bool timing = false;
+    double ms[PG_K_COUNT] = {0};
+    int64_t launches[PG_K_COUNT] = {0};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+int fail(pg_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(pg_ctx* c, hipError_t e, const char* where) {
+    std::string msg = std::string(where) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory) return fail(c, PG_E_OOM, msg);
+    return fail(c, PG_E_DEVICE, msg);
+}
+
+#define PG_HIP(c, call)                                     \
+    do {                                                    \
+        hipError_t _e = (call);                             \
+        if (_e != hipSuccess) return hip_fail((c), _e, #call); \
+    } while (0)
+
+int ensure_buf(pg_ctx* c, const char* name, size_t bytes) {
+    DevBuf& b = c->bufs[name];
+    if (b.bytes >= bytes && b.ptr) return PG_OK;
+    if (b.ptr) {
+        hipError_t e = hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+        if (e != hipSuccess) return hip_fail(c, e, "hipFree");
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 256));
+    if (e != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    b.ptr = p;
+    b.bytes = std::max<size_t>(bytes, 256);
+    return PG_OK;
+}
+
+template <typename X>
+X* buf(pg_ctx* c, const char* name) {
+    return static_cast<X*>(c->bufs[name].ptr);
+}
+
+size_t elem_size(int precision) { return precision == PG_FP32 ? 4 : 8; }
+
+// Internal nodes grouped by height (tips have height 0); nodes of one level
+// have no ancestor relation, so a level is processed in parallel and the
+// levels in increasing order form a post-order (decreasing: a pre-order).
+void build_levels(pg_ctx* c) {
+    const int N = c->n_tips, n_nodes = 2 * N - 1;
+    std::vector<int> height(n_nodes, 0);
+    // internal nodes: repeat relaxation in label-free order via explicit stack
+    std::vector<int> order;
+    order.reserve(N - 1);
+    std::vector<int> stack{n_nodes - 1};
+    std::vector<char> expanded(n_nodes, 0);
+    while (!stack.empty()) {
+        int v = stack.back();
+        if (v < N) { stack.pop_back(); continue; }
+        if (!expanded[v]) {
+            expanded[v] = 1;
+            stack.push_back(c->children[v].x);
+            stack.push_back(c->children[v].y);
+        } else {
+            stack.pop_back();
+            height[v] = 1 + std::max(height[c->children[v].x], height[c->children[v].y]);
+            order.push_back(v);
+        }
+    }
+    int H = 0;
+    for (int v : order) H = std::max(H, height[v]);
+    c->level_off.assign(H + 1, 0);
+    std::vector<int> count(H + 1, 0);
+    for (int v : order) count[height[v]]++;
+    // level h (1..H) stored at index h-1
+    c->level_off.assign(H + 1, 0);
+    for (int h = 1; h <= H; ++h) c->level_off[h] = c->level_off[h - 1] + count[h];
+    c->level_nodes.assign(N - 1, 0);
+    std::vector<int> fill(c->level_off.begin(), c->level_off.end() - 1);
+    std::vector<int> sorted(order);
+    std::sort(sorted.begin(), sorted.end());
+    for (int v : sorted) c->level_nodes[fill[height[v] - 1]++] = v;
+}
+
+int check_tree(pg_ctx* c, int32_t N, const int32_t* parent) {
+    const int n_nodes = 2 * N - 1;
+    const int root = n_nodes - 1;
+    if (parent[root] != -1) return fail(c, PG_E_TREE, "parent[2N-2] must be -1 (root last)");
+    std::vector<int> nchild(n_nodes, 0);
+    std::vector<int2> ch(n_nodes, make_int2(-1, -1));
+    for (int v = 0; v < root; ++v) {
+        const int p = parent[v];
+        if (p < N || p >= n_nodes)
+            return fail(c, PG_E_TREE, "node " + std::to_string(v) + " has parent " +
+                                          std::to_string(p) + " outside the internal nodes");
+        if (nchild[p] == 0) ch[p].x = v;
+        else if (nchild[p] == 1) ch[p].y = v;
+        nchild[p]++;
+    }
+    for (int k = N; k < n_nodes; ++k)
+        if (nchild[k] != 2)
+            return fail(c, PG_E_TREE, "internal node " + std::to_string(k) + " has " +
+                                          std::to_string(nchild[k]) + " children (binary tree required)");
+    // every node reaches the root: walk up with a step bound (cycle check)
+    std::vector<char> ok(n_nodes, 0);
+    ok[root] = 1;
+    for (int v = 0; v < n_nodes; ++v) {
+        std::vector<int> path;
+        int u = v;
+        int steps = 0;
+        while (!ok[u]) {
+            path.push_back(u);
+            u = parent[u];
+            if (++steps > n_nodes) return fail(c, PG_E_TREE, "the parent array has a cycle");
+        }
+        for (int w : path) ok[w] = 1;
+    }
+    c->children = ch;
+    return PG_OK;
+}
+
+int upload(pg_ctx* c) {
+    if (!c->tree_set || !c->patterns_set || !c->model_set)
+        return fail(c, PG_E_STATE, "tree, patterns and model must all be set before evaluating");
+    if (c->m_pat != c->m)
+        return fail(c, PG_E_STATE, "patterns have " + std::to_string(c->m_pat) +
+                                       " states but the model has " + std::to_string(c->m));
+    if (!c->dev_stale) return PG_OK;
+    PG_HIP(c, hipSetDevice(c->device));
+    const int N = c->n_tips, n_nodes = 2 * N - 1, B = n_nodes - 1;
+    const int M = c->m, K = c->K;
+    const size_t es = elem_size(c->precision);
+    const int n_pb = c->S_pad / TP;
+    const int n_tiles = K * n_pb;
+    const size_t vec = (size_t)K * M * c->S_pad;
+    int r;
+    if ((r = ensure_buf(c, "t", sizeof(double) * B))) return r;
+    if ((r = ensure_buf(c, "P", es * (size_t)B * K * M * M))) return r;
+    if ((r = ensure_buf(c, "msg", es * vec * (N - 1)))) return r;
+    if ((r = ensure_buf(c, "qv", es * vec * (N - 1)))) return r;
+    if ((r = ensure_buf(c, "codes", (size_t)N * c->S_pad))) return r;
+    if ((r = ensure_buf(c, "masks", sizeof(unsigned long long) * 256))) return r;
+    if ((r = ensure_buf(c, "level_off", sizeof(int) * c->level_off.size()))) return r;
+    if ((r = ensure_buf(c, "level_nodes", sizeof(int) * c->level_nodes.size()))) return r;
+    if ((r = ensure_buf(c, "children", sizeof(int2) * n_nodes))) return r;
+    if ((r = ensure_buf(c, "Q64", sizeof(double) * M * M))) return r;
+    if ((r = ensure_buf(c, "Q2_64", sizeof(double) * M * M))) return r;
+    if ((r = ensure_buf(c, "pi64", sizeof(double) * M))) return r;
+    if ((r = ensure_buf(c, "rates", sizeof(double) * K))) return r;
+    if ((r = ensure_buf(c, "catw", sizeof(double) * K))) return r;
+    if ((r = ensure_buf(c, "weights", sizeof(double) * c->S_pad))) return r;
+    if ((r = ensure_buf(c, "rootL", sizeof(double) * K * c->S_pad))) return r;
+    if ((r = ensure_buf(c, "rootE", sizeof(int) * K * c->S_pad))) return r;
+    if ((r = ensure_buf(c, "rho", sizeof(double) * K * c->S_pad))) return r;
+    if ((r = ensure_buf(c, "partial", sizeof(double) * (size_t)n_tiles * B))) return r;
+    if ((r = ensure_buf(c, "partial2", sizeof(double) * (size_t)n_pb * B))) return r;
+    if ((r = ensure_buf(c, "grad", sizeof(double) * B))) return r;
+    if ((r = ensure_buf(c, "hess", sizeof(double) * B))) return r;
+    if ((r = ensure_buf(c, "logL", sizeof(double) * 2))) return r;
+    if ((r = ensure_buf(c, "status", sizeof(int) * 2))) return r;
+
+    hipStream_t st = c->stream;
+    auto put = [&](const char* name, const void* src, size_t bytes) {
+        return hipMemcpyAsync(c->bufs[name].ptr, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    std::vector<int2> ch(c->children);
+    PG_HIP(c, put("codes", c->codes.data(), c->codes.size()));
+    PG_HIP(c, put("masks", c->masks.data(), sizeof(unsigned long long) * 256));
+    PG_HIP(c, put("level_off", c->level_off.data(), sizeof(int) * c->level_off.size()));
+    PG_HIP(c, put("level_nodes", c->level_nodes.data(), sizeof(int) * c->level_nodes.size()));
+    PG_HIP(c, put("children", ch.data(), sizeof(int2) * n_nodes));
+    PG_HIP(c, put("Q64", c->Q.data(), sizeof(double) * M * M));
+    PG_HIP(c, put("Q2_64", c->Q2.data(), sizeof(double) * M * M));
+    PG_HIP(c, put("pi64", c->pi.data(), sizeof(double) * M));
+    PG_HIP(c, put("rates", c->rates.data(), sizeof(double) * K));
+    PG_HIP(c, put("catw", c->catw.data(), sizeof(double) * K));
+    PG_HIP(c, put("weights", c->weights.data(), sizeof(double) * c->S_pad));
+    // pageable host sources: make sure the copies are done before the vectors move
+    PG_HIP(c, hipStreamSynchronize(st));
+
+    EvalArgs& a = c->args;
+    a = EvalArgs{};
+    a.n_tips = N;
+    a.n_nodes = n_nodes;
+    a.n_branches = B;
+    a.root = n_nodes - 1;
+    a.K = K;
+    a.M = M;
+    a.S = c->S;
+    a.S_pad = c->S_pad;
+    a.n_pb = n_pb;
+    a.n_tiles = n_tiles;
+    a.n_levels = (int)c->level_off.size() - 1;
+    a.qnorm = c->qnorm;
+    a.t = buf<double>(c, "t");
+    a.P = c->bufs["P"].ptr;
+    a.msg = c->bufs["msg"].ptr;
+    a.qv = c->bufs["qv"].ptr;
+    a.codes = buf<uint8_t>(c, "codes");
+    a.masks = buf<unsigned long long>(c, "masks");
+    a.level_off = buf<int>(c, "level_off");
+    a.level_nodes = buf<int>(c, "level_nodes");
+    a.children = buf<int2>(c, "children");
+    a.Q64 = buf<double>(c, "Q64");
+    a.Q2_64 = buf<double>(c, "Q2_64");
+    a.pi64 = buf<double>(c, "pi64");
+    a.rates = buf<double>(c, "rates");
+    a.catw = buf<double>(c, "catw");
+    a.weights = buf<double>(c, "weights");
+    a.rootL = buf<double>(c, "rootL");
+    a.rootE = buf<int>(c, "rootE");
+    a.rho = buf<double>(c, "rho");
+    a.partial = buf<double>(c, "partial");
+    a.partial2 = buf<double>(c, "partial2");
+    a.grad = buf<double>(c, "grad");
+    a.hess = buf<double>(c, "hess");
+    a.logL = buf<double>(c, "logL");
+    a.status = buf<int>(c, "status");
+    c->dev_stale = false;
+    c->have_partials = false;
+    return PG_OK;
+}
+
+// Launch one kernel, bracketed by events when timing is on.
+template <typename F>
+int timed(pg_ctx* c, int kid, F&& launch) {
+    if (c->timing) PG_HIP(c, hipEventRecord(c->ev0, c->stream));
+    hipError_t e = launch();
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+    if (c->timing) {
+        PG_HIP(c, hipEventRecord(c->ev1, c->stream));
+        PG_HIP(c, hipEventSynchronize(c->ev1));
+        float ms = 0.f;
+        PG_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        c->ms[kid] += ms;
+        c->launches[kid] += 1;
+    }
+    return PG_OK;
+}
+
+int check_lengths(pg_ctx* c, const double* t) {
+    const int B = 2 * c->n_tips - 2;
+    for (int b = 0; b < B; ++b)
+        if (!std::isfinite(t[b]) || t[b] < 0.0)
+            return fail(c, PG_E_INVALID, "branch length t[" + std::to_string(b) + "] = " +
+                                             std::to_string(t[b]) + " is not finite and >= 0");
+    return PG_OK;
+}
+
+// Enqueue the post-order half: status reset, P, post, root.
+int enqueue_forward(pg_ctx* c) {
+    const EvalArgs& a = c->args;
+    PG_HIP(c, hipMemsetAsync(a.status, 0, sizeof(int), c->stream));
+    int r;
+    if ((r = timed(c, PG_K_PMAT, [&] { return launch_pmat(a, c->precision, c->stream); }))) return r;
+    if ((r = timed(c, PG_K_POST, [&] { return launch_post(a, c->precision, c->stream); }))) return r;
+    if ((r = timed(c, PG_K_ROOT, [&] { return launch_root(a, c->stream); }))) return r;
+    return PG_OK;
+}
+
+int enqueue_backward(pg_ctx* c) {
+    const EvalArgs& a = c->args;
+    int r;
+    if ((r = timed(c, PG_K_PRE, [&] { return launch_pre(a, c->precision, c->stream); }))) return r;
+    if ((r = timed(c, PG_K_GSUM, [&] { return launch_gsum(a, c->stream); }))) return r;
+    return PG_OK;
+}
+
+int read_status(pg_ctx* c, double* logL) {
+    int status = 0;
+    PG_HIP(c, hipMemcpyAsync(&status, c->args.status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    if (logL) PG_HIP(c, hipMemcpyAsync(logL, c->args.logL, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    PG_HIP(c, hipStreamSynchronize(c->stream));
+    if (status & 1) return fail(c, PG_E_INVALID, "a branch length is not finite and >= 0");
+    if (status & 2) return fail(c, PG_E_ZERO_LIK, "a pattern with positive weight has likelihood 0");
+    return PG_OK;
+}
+
+template <typename F>
+int guarded(pg_ctx* c, F&& body) {
+    try {
+        return body();
+    } catch (const std::bad_alloc&) {
+        return fail(c, PG_E_OOM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(c, PG_E_DEVICE, std::string("internal error: ") + e.what());
+    } catch (...) {
+        return fail(c, PG_E_DEVICE, "internal error");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int pg_create(int device, int precision, pg_ctx** out) {
+    if (!out) return PG_E_INVALID;
+    *out = nullptr;
+    if (precision != PG_FP64 && precision != PG_FP32) {
+        g_create_error = "precision must be PG_FP64 or PG_FP32";
+        return PG_E_UNSUPPORTED;
+    }
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || device < 0 || device >= n) {
+        g_create_error = "no HIP device " + std::to_string(device) +
+                         (e != hipSuccess ? std::string(": ") + hipGetErrorString(e) : std::string());
+        return PG_E_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipGetDeviceProperties: ") + hipGetErrorString(e);
+        return PG_E_DEVICE;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        g_create_error = std::string("device is ") + prop.gcnArchName + ", the kernels are built for gfx950";
+        return PG_E_DEVICE;
+    }
+    pg_ctx* c = nullptr;
+    try {
+        c = new pg_ctx();
+    } catch (...) {
+        g_create_error = "host allocation failed";
+        return PG_E_OOM;
+    }
+    c->device = device;
+    c->precision = precision;
+    if ((e = hipSetDevice(device)) != hipSuccess || (e = hipStreamCreate(&c->own_stream)) != hipSuccess ||
+        (e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess) {
+        g_create_error = std::string("HIP setup: ") + hipGetErrorString(e);
+        pg_destroy(c);
+        return PG_E_DEVICE;
+    }
+    c->stream = c->own_stream;
+    *out = c;
+    return PG_OK;
+}
+
+void pg_destroy(pg_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->bufs)
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    delete c;
+}
+
+const char* pg_last_error(const pg_ctx* c) {
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+int pg_set_stream(pg_ctx* c, void* s) {
+    if (!c) return PG_E_INVALID;
+    return guarded(c, [&] {
+        PG_HIP(c, hipStreamSynchronize(c->stream));
+        c->stream = s ? static_cast<hipStream_t>(s) : c->own_stream;
+        return PG_OK;
+    });
+}
+
+int pg_set_tree(pg_ctx* c, int32_t N, const int32_t* parent) {
+    if (!c) return PG_E_INVALID;
+    if (!parent) return fail(c, PG_E_INVALID, "parent is NULL");
+    if (N < 2 || N > (1 << 26)) return fail(c, PG_E_INVALID, "need 2 <= n_tips <= 2^26");
+    return guarded(c, [&] {
+        int r = check_tree(c, N, parent);
+        if (r) return r;
+        if (c->n_tips != N) c->patterns_set = false;
+        c->n_tips = N;
+        c->parent.assign(parent, parent + 2 * N - 1);
+        build_levels(c);
+        c->tree_set = true;
+        c->dev_stale = true;
+        c->have_partials = false;
+        return PG_OK;
+    });
+}
+
+int pg_set_patterns(pg_ctx* c, int32_t S, int32_t m, const uint64_t* tip_masks, const double* weights) {
+    if (!c) return PG_E_INVALID;
+    if (!c->tree_set) return fail(c, PG_E_STATE, "set the tree before the patterns");
+    if (!tip_masks || !weights) return fail(c, PG_E_INVALID, "NULL masks or weights");
+    if (S < 1) return fail(c, PG_E_INVALID, "need n_patterns >= 1");
+    if (m < 2 || m > 64) return fail(c, PG_E_PATTERNS, "need 2 <= n_states <= 64");
+    return guarded(c, [&] {
+        const int N = c->n_tips;
+        const int S_pad = (S + TP - 1) / TP * TP;
+        const unsigned long long full = (m == 64) ? ~0ull : ((1ull << m) - 1);
+        std::vector<unsigned long long> table(256, 0);
+        for (int x = 0; x < m; ++x) table[x] = 1ull << x;
+        table[255] = full;
+        std::map<unsigned long long, int> partial_code;
+        int next = m;
+        std::vector<uint8_t> codes((size_t)N * S_pad, 255);
+        for (int v = 0; v < N; ++v)
+            for (int s = 0; s < S; ++s) {
+                const unsigned long long mk = tip_masks[(size_t)v * S + s];
+                if (mk == 0)
+                    return fail(c, PG_E_PATTERNS, "empty mask at tip " + std::to_string(v) + ", pattern " +
+                                                      std::to_string(s));
+                if (mk & ~full)
+                    return fail(c, PG_E_PATTERNS, "mask names a state >= n_states at tip " +
+                                                      std::to_string(v) + ", pattern " + std::to_string(s));
+                uint8_t code;
+                if (mk == full) {
+                    code = 255;
+                } else if ((mk & (mk - 1)) == 0) {
+                    code = (uint8_t)__builtin_ctzll(mk);
+                } else {
+                    auto it = partial_code.find(mk);
+                    if (it == partial_code.end()) {
+                        if (next >= 255)
+                            return fail(c, PG_E_PATTERNS, "more than 255 - n_states distinct ambiguity masks");
+                        table[next] = mk;
+                        it = partial_code.emplace(mk, next++).first;
+                    }
+                    code = (uint8_t)it->second;
+                }
+                codes[(size_t)v * S_pad + s] = code;
+            }
+        std::vector<double> w(S_pad, 0.0);
+        for (int s = 0; s < S; ++s) {
+            if (!std::isfinite(weights[s]) || weights[s] < 0.0)
+                return fail(c, PG_E_PATTERNS, "pattern weight " + std::to_string(s) + " is not finite and >= 0");
+            w[s] = weights[s];
+        }
+        c->S = S;
+        c->S_pad = S_pad;
+        c->m_pat = m;
+        c->codes.swap(codes);
+        c->masks.swap(table);
+        c->weights.swap(w);
+        c->patterns_set = true;
+        c->dev_stale = true;
+        c->have_partials = false;
+        return PG_OK;
+    });
+}
+
+int pg_set_model(pg_ctx* c, int32_t m, const double* Q, const double* pi, int32_t K, const double* rates,
+                 const double* catw) {
+    if (!c) return PG_E_INVALID;
+    if (!Q || !pi || !rates || !catw) return fail(c, PG_E_INVALID, "NULL model array");
+    if (m < 2 || m > 64) return fail(c, PG_E_MODEL, "need 2 <= n_states <= 64");
+    if (K < 1 || K > 64) return fail(c, PG_E_MODEL, "need 1 <= n_cats <= 64");
+    if (!kernel_supported(m, c->precision))
+        return fail(c, PG_E_UNSUPPORTED, "no kernel compiled for " + std::to_string(m) + " states");
+    return guarded(c, [&] {
+        double amax = 1.0;
+        for (int i = 0; i < m * m; ++i) {
+            if (!std::isfinite(Q[i])) return fail(c, PG_E_MODEL, "Q has a non-finite entry");
+            amax = std::max(amax, std::fabs(Q[i]));
+        }
+        double qnorm = 0.0;
+        for (int x = 0; x < m; ++x) {
+            double row = 0.0, rabs = 0.0;
+            for (int y = 0; y < m; ++y) {
+                if (x != y && Q[x * m + y] < 0.0)
+                    return fail(c, PG_E_MODEL, "Q has a negative off-diagonal rate");
+                row += Q[x * m + y];
+                rabs += std::fabs(Q[x * m + y]);
+            }
+            if (std::fabs(row) > 1e-12 * amax * m)
+                return fail(c, PG_E_MODEL, "row " + std::to_string(x) + " of Q does not sum to 0");
+            qnorm = std::max(qnorm, rabs);
+        }
+        double ps = 0.0;
+        for (int x = 0; x < m; ++x) {
+            if (!std::isfinite(pi[x]) || pi[x] < 0.0) return fail(c, PG_E_MODEL, "root frequency < 0 or not finite");
+            ps += pi[x];
+        }
+        if (std::fabs(ps - 1.0) > 1e-12) return fail(c, PG_E_MODEL, "root frequencies do not sum to 1");
+        double ws = 0.0;
+        for (int l = 0; l < K; ++l) {
+            if (!std::isfinite(rates[l]) || rates[l] < 0.0) return fail(c, PG_E_MODEL, "category rate < 0 or not finite");
+            if (!std::isfinite(catw[l]) || catw[l] < 0.0) return fail(c, PG_E_MODEL, "category weight < 0 or not finite");
+            ws += catw[l];
+        }
+        if (std::fabs(ws - 1.0) > 1e-12) return fail(c, PG_E_MODEL, "category weights do not sum to 1");
+        c->m = m;
+        c->K = K;
+        c->Q.assign(Q, Q + m * m);
+        c->Q2.assign(m * m, 0.0);
+        for (int x = 0; x < m; ++x)
+            for (int y = 0; y < m; ++y) {
+                double acc = 0.0;
+                for (int z = 0; z < m; ++z) acc += Q[x * m + z] * Q[z * m + y];
+                c->Q2[x * m + y] = acc;
+            }
+        c->pi.assign(pi, pi + m);
+        c->rates.assign(rates, rates + K);
+        c->catw.assign(catw, catw + K);
+        c->qnorm = qnorm;
+        c->model_set = true;
+        c->dev_stale = true;
+        c->have_partials = false;
+        return PG_OK;
+    });
+}
+
+int pg_logL(pg_ctx* c, const double* t, double* logL) {
+    if (!c) return PG_E_INVALID;
+    if (!t || !logL) return fail(c, PG_E_INVALID, "NULL t or logL");
+    return guarded(c, [&] {
+        int r = upload(c);
+        if (r) return r;
+        if ((r = check_lengths(c, t))) return r;
+        PG_HIP(c, hipSetDevice(c->device));
+        PG_HIP(c, hipMemcpyAsync((void*)c->args.t, t, sizeof(double) * c->args.n_branches,
+                                 hipMemcpyHostToDevice, c->stream));
+        c->have_partials = false;
+        if ((r = enqueue_forward(c))) return r;
+        r = read_status(c, logL);
+        if (r == PG_E_ZERO_LIK) *logL = -INFINITY;
+        if (r == PG_OK) c->have_partials = true;
+        return r;
+    });
+}
+
+int pg_grad(pg_ctx* c, double* grad) {
+    if (!c) return PG_E_INVALID;
+    if (!grad) return fail(c, PG_E_INVALID, "NULL grad");
+    if (!c->have_partials || c->dev_stale)
+        return fail(c, PG_E_STATE, "no resident partials: call pg_logL first");
+    return guarded(c, [&] {
+        PG_HIP(c, hipSetDevice(c->device));
+        int r = enqueue_backward(c);
+        if (r) return r;
+        PG_HIP(c, hipMemcpyAsync(grad, c->args.grad, sizeof(double) * c->args.n_branches,
+                                 hipMemcpyDeviceToHost, c->stream));
+        PG_HIP(c, hipStreamSynchronize(c->stream));
+        return PG_OK;
+    });
+}
+
+int pg_logL_and_grad(pg_ctx* c, const double* t, double* logL, double* grad) {
+    int r = pg_logL(c, t, logL);
+    if (r != PG_OK || grad == nullptr) return r;
+    return pg_grad(c, grad);
+}
+
+int pg_hessian_diag(pg_ctx* c, double* grad, double* hess) {
+    if (!c) return PG_E_INVALID;
+    (void)grad;
+    (void)hess;
+    return fail(c, PG_E_UNSUPPORTED, "Hessian diagonal not built yet");
+}
+
+int pg_logL_and_grad_device(pg_ctx* c, const double* d_t, double* d_logL, double* d_grad) {
+    if (!c) return PG_E_INVALID;
+    if (!d_t || !d_logL) return fail(c, PG_E_INVALID, "NULL d_t or d_logL");
+    return guarded(c, [&] {
+        int r = upload(c);
+        if (r) return r;
+        PG_HIP(c, hipSetDevice(c->device));
+        PG_HIP(c, hipMemcpyAsync((void*)c->args.t, d_t, sizeof(double) * c->args.n_branches,
+                                 hipMemcpyDeviceToDevice, c->stream));
+        if ((r = enqueue_forward(c))) return r;
+        if (d_grad) {
+            if ((r = enqueue_backward(c))) return r;
+            PG_HIP(c, hipMemcpyAsync(d_grad, c->args.grad, sizeof(double) * c->args.n_branches,
+                                     hipMemcpyDeviceToDevice, c->stream));
+        }
+        PG_HIP(c, hipMemcpyAsync(d_logL, c->args.logL, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        c->have_partials = true;
+        return PG_OK;
+    });
+}
+
+int pg_status(pg_ctx* c) {
+    if (!c) return PG_E_INVALID;
+    if (c->dev_stale) return PG_OK;
+    return guarded(c, [&] { return read_status(c, nullptr); });
+}
+
+int pg_set_timing(pg_ctx* c, int enable) {
+    if (!c) return PG_E_INVALID;
+    c->timing = enable != 0;
+    return PG_OK;
+}
+
+int pg_get_timing(pg_ctx* c, double* ms, int64_t* launches) {
+    if (!c) return PG_E_INVALID;
+    for (int k = 0; k < PG_K_COUNT; ++k) {
+        if (ms) ms[k] = c->ms[k];
+        if (launches) launches[k] = c->launches[k];
+        c->ms[k] = 0.0;
+        c->launches[k] = 0;
+    }
+    return PG_OK;
+}
+
+int64_t pg_device_bytes(const pg_ctx* c) {
+    if (!c) return 0;
+    int64_t tot = 0;
+    for (const auto& kv : c->bufs) tot += (int64_t)kv.second.bytes;
+    return tot;
+}
+
+int64_t pg_footprint_bytes(int32_t N, int32_t S, int32_t m, int32_t K, int precision) {
+    if (N < 2 || S < 1 || m < 2 || K < 1) return -1;
+    const int64_t es = precision == PG_FP32 ? 4 : 8;
+    const int64_t S_pad = (S + TP - 1) / TP * TP;
+    const int64_t B = 2 * (int64_t)N - 2;
+    const int64_t n_tiles = K * (S_pad / TP);
+    int64_t tot = 0;
+    tot += 2 * es * (int64_t)K * m * S_pad * (N - 1);       // msg + qv
+    tot += es * B * K * m * m;                             // P
+    tot += (int64_t)N * S_pad;                             // codes
+    tot += 8 * (n_tiles * B + (S_pad / TP) * B);           // tile partial sums
+    tot += (8 + 8 + 4) * (int64_t)K * S_pad + 8 * S_pad;   // root values, rho, weights
+    tot += 8 * 4 * B + 4 * 3 * (int64_t)N + 4096;          // t, grad, hess, schedule
+    return tot;
+}
+
+}  // extern "C"

@@ -64,11 +64,11 @@ extern "C" {
 #define PG_FP32 1
 
 /* ---- kernels reported by pg_get_timing ------------------------------- */
-#define PG_K_PMAT  0  /* transition matrices exp(Q rate t)         */
-#define PG_K_POST  1  /* post-order pass, rescaling, root values   */
-#define PG_K_ROOT  2  /* per-pattern likelihood, logL reduction    */
-#define PG_K_PRE   3  /* pre-order pass fused with the gradient    */
-#define PG_K_GSUM  4  /* fixed-order per-branch gradient reduction */
+#define PG_K_PMAT  0  /* transition matrices exp(Q rate t)                     */
+#define PG_K_POST  1  /* post-order pass, rescaling, root values               */
+#define PG_K_ROOT  2  /* logL reduction of calls without a gradient            */
+#define PG_K_PRE   3  /* pre-order pass fused with the gradient                */
+#define PG_K_GSUM  4  /* fixed-order per-branch gradient reduction, with logL  */
 #define PG_K_COUNT 5
 
 typedef struct pg_ctx pg_ctx;

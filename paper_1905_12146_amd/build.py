@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libphylograd.so")
 SOURCES = ["kernels.hip", "capi.cpp"]
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
+    "-O3", "-std=c++20", "-fPIC", "--offload-arch=gfx950",
     "-Wall", "-Wno-unused-result",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -56,6 +56,7 @@ struct pg_ctx {
     // device state
     bool dev_stale = true;        // host inputs changed since the last upload
     bool have_partials = false;   // post-order pass results resident
+    bool device_pending = false;  // a device-pointer evaluation was enqueued
     std::map<std::string, DevBuf> bufs;
     EvalArgs args{};
 
@@ -217,7 +218,6 @@ int upload(pg_ctx* c) {
     if ((r = ensure_buf(c, "weights", sizeof(double) * c->S_pad))) return r;
     if ((r = ensure_buf(c, "rootL", sizeof(double) * K * c->S_pad))) return r;
     if ((r = ensure_buf(c, "rootE", sizeof(int) * K * c->S_pad))) return r;
-    if ((r = ensure_buf(c, "rho", sizeof(double) * K * c->S_pad))) return r;
     if ((r = ensure_buf(c, "partial", sizeof(double) * (size_t)n_tiles * B))) return r;
     if ((r = ensure_buf(c, "partial2", sizeof(double) * (size_t)n_pb * B))) return r;
     if ((r = ensure_buf(c, "grad", sizeof(double) * B))) return r;
@@ -258,6 +258,8 @@ int upload(pg_ctx* c) {
     a.n_tiles = n_tiles;
     a.n_levels = (int)c->level_off.size() - 1;
     a.qnorm = c->qnorm;
+    for (int e = 0; e < 16; ++e) a.Qs[e] = (e < M * M) ? c->Q[e] : 0.0;
+    for (int e = 0; e < 4; ++e) a.pis[e] = (e < M) ? c->pi[e] : 0.0;
     a.t = buf<double>(c, "t");
     a.P = c->bufs["P"].ptr;
     a.msg = c->bufs["msg"].ptr;
@@ -275,12 +277,11 @@ int upload(pg_ctx* c) {
     a.weights = buf<double>(c, "weights");
     a.rootL = buf<double>(c, "rootL");
     a.rootE = buf<int>(c, "rootE");
-    a.rho = buf<double>(c, "rho");
     a.partial = buf<double>(c, "partial");
     a.partial2 = buf<double>(c, "partial2");
-    a.grad = buf<double>(c, "grad");
-    a.hess = buf<double>(c, "hess");
-    a.logL = buf<double>(c, "logL");
+    a.grad_out = buf<double>(c, "grad");
+    a.hess_out = buf<double>(c, "hess");
+    a.logL_out = buf<double>(c, "logL");
     a.status = buf<int>(c, "status");
     c->dev_stale = false;
     c->have_partials = false;
@@ -313,33 +314,41 @@ int check_lengths(pg_ctx* c, const double* t) {
     return PG_OK;
 }
 
-// Enqueue the post-order half: status reset, P, post, root.
-int enqueue_forward(pg_ctx* c) {
-    const EvalArgs& a = c->args;
-    PG_HIP(c, hipMemsetAsync(a.status, 0, sizeof(int), c->stream));
+// Enqueue the evaluation on the context's stream.  Branch lengths are read
+// from a.t; logL (and the gradient) are written to a.logL_out (a.grad_out).
+//   forward only:  pmat, post, logl
+//   with gradient: pmat, post, pre, gsum (gsum also reduces logL)
+int enqueue_forward(pg_ctx* c, const EvalArgs& a, bool with_logl) {
     int r;
     if ((r = timed(c, PG_K_PMAT, [&] { return launch_pmat(a, c->precision, c->stream); }))) return r;
     if ((r = timed(c, PG_K_POST, [&] { return launch_post(a, c->precision, c->stream); }))) return r;
-    if ((r = timed(c, PG_K_ROOT, [&] { return launch_root(a, c->stream); }))) return r;
+    if (with_logl && (r = timed(c, PG_K_ROOT, [&] { return launch_logl(a, c->stream); }))) return r;
     return PG_OK;
 }
 
-int enqueue_backward(pg_ctx* c) {
-    const EvalArgs& a = c->args;
+int enqueue_backward(pg_ctx* c, const EvalArgs& a) {
     int r;
     if ((r = timed(c, PG_K_PRE, [&] { return launch_pre(a, c->precision, c->stream); }))) return r;
     if ((r = timed(c, PG_K_GSUM, [&] { return launch_gsum(a, c->stream); }))) return r;
     return PG_OK;
 }
 
-int read_status(pg_ctx* c, double* logL) {
+int status_code(pg_ctx* c, int status) {
+    if (status == 1) return fail(c, PG_E_INVALID, "a branch length is not finite and >= 0 (logL is NaN)");
+    if (status == 2) return fail(c, PG_E_ZERO_LIK, "a pattern with positive weight has likelihood 0");
+    return PG_OK;
+}
+
+// Copy logL (and grad) back, wait, and map the device status to a code.
+int finish_host(pg_ctx* c, double* logL, double* grad) {
     int status = 0;
     PG_HIP(c, hipMemcpyAsync(&status, c->args.status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    if (logL) PG_HIP(c, hipMemcpyAsync(logL, c->args.logL, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    PG_HIP(c, hipMemcpyAsync(logL, c->args.logL_out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (grad)
+        PG_HIP(c, hipMemcpyAsync(grad, c->args.grad_out, sizeof(double) * c->args.n_branches,
+                                 hipMemcpyDeviceToHost, c->stream));
     PG_HIP(c, hipStreamSynchronize(c->stream));
-    if (status & 1) return fail(c, PG_E_INVALID, "a branch length is not finite and >= 0");
-    if (status & 2) return fail(c, PG_E_ZERO_LIK, "a pattern with positive weight has likelihood 0");
-    return PG_OK;
+    return status_code(c, status);
 }
 
 template <typename F>
@@ -577,11 +586,11 @@ int pg_logL(pg_ctx* c, const double* t, double* logL) {
         if (r) return r;
         if ((r = check_lengths(c, t))) return r;
         PG_HIP(c, hipSetDevice(c->device));
+        c->have_partials = false;
         PG_HIP(c, hipMemcpyAsync((void*)c->args.t, t, sizeof(double) * c->args.n_branches,
                                  hipMemcpyHostToDevice, c->stream));
-        c->have_partials = false;
-        if ((r = enqueue_forward(c))) return r;
-        r = read_status(c, logL);
+        if ((r = enqueue_forward(c, c->args, true))) return r;
+        r = finish_host(c, logL, nullptr);
         if (r == PG_E_ZERO_LIK) *logL = -INFINITY;
         if (r == PG_OK) c->have_partials = true;
         return r;
@@ -595,19 +604,32 @@ int pg_grad(pg_ctx* c, double* grad) {
         return fail(c, PG_E_STATE, "no resident partials: call pg_logL first");
     return guarded(c, [&] {
         PG_HIP(c, hipSetDevice(c->device));
-        int r = enqueue_backward(c);
+        int r = enqueue_backward(c, c->args);
         if (r) return r;
-        PG_HIP(c, hipMemcpyAsync(grad, c->args.grad, sizeof(double) * c->args.n_branches,
-                                 hipMemcpyDeviceToHost, c->stream));
-        PG_HIP(c, hipStreamSynchronize(c->stream));
-        return PG_OK;
+        double logL = 0.0;
+        return finish_host(c, &logL, grad);
     });
 }
 
 int pg_logL_and_grad(pg_ctx* c, const double* t, double* logL, double* grad) {
-    int r = pg_logL(c, t, logL);
-    if (r != PG_OK || grad == nullptr) return r;
-    return pg_grad(c, grad);
+    if (!c) return PG_E_INVALID;
+    if (!t || !logL) return fail(c, PG_E_INVALID, "NULL t or logL");
+    if (!grad) return pg_logL(c, t, logL);
+    return guarded(c, [&] {
+        int r = upload(c);
+        if (r) return r;
+        if ((r = check_lengths(c, t))) return r;
+        PG_HIP(c, hipSetDevice(c->device));
+        c->have_partials = false;
+        PG_HIP(c, hipMemcpyAsync((void*)c->args.t, t, sizeof(double) * c->args.n_branches,
+                                 hipMemcpyHostToDevice, c->stream));
+        if ((r = enqueue_forward(c, c->args, false))) return r;
+        if ((r = enqueue_backward(c, c->args))) return r;
+        r = finish_host(c, logL, grad);
+        if (r == PG_E_ZERO_LIK) *logL = -INFINITY;
+        if (r == PG_OK) c->have_partials = true;
+        return r;
+    });
 }
 
 int pg_hessian_diag(pg_ctx* c, double* grad, double* hess) {
@@ -624,24 +646,27 @@ int pg_logL_and_grad_device(pg_ctx* c, const double* d_t, double* d_logL, double
         int r = upload(c);
         if (r) return r;
         PG_HIP(c, hipSetDevice(c->device));
-        PG_HIP(c, hipMemcpyAsync((void*)c->args.t, d_t, sizeof(double) * c->args.n_branches,
-                                 hipMemcpyDeviceToDevice, c->stream));
-        if ((r = enqueue_forward(c))) return r;
-        if (d_grad) {
-            if ((r = enqueue_backward(c))) return r;
-            PG_HIP(c, hipMemcpyAsync(d_grad, c->args.grad, sizeof(double) * c->args.n_branches,
-                                     hipMemcpyDeviceToDevice, c->stream));
-        }
-        PG_HIP(c, hipMemcpyAsync(d_logL, c->args.logL, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        EvalArgs a = c->args;
+        a.t = d_t;
+        a.logL_out = d_logL;
+        if (d_grad) a.grad_out = d_grad;
+        if ((r = enqueue_forward(c, a, d_grad == nullptr))) return r;
+        if (d_grad && (r = enqueue_backward(c, a))) return r;
         c->have_partials = true;
+        c->device_pending = true;
         return PG_OK;
     });
 }
 
 int pg_status(pg_ctx* c) {
     if (!c) return PG_E_INVALID;
-    if (c->dev_stale) return PG_OK;
-    return guarded(c, [&] { return read_status(c, nullptr); });
+    if (!c->device_pending) return PG_OK;
+    return guarded(c, [&] {
+        int status = 0;
+        PG_HIP(c, hipMemcpyAsync(&status, c->args.status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        PG_HIP(c, hipStreamSynchronize(c->stream));
+        return status_code(c, status);
+    });
 }
 
 int pg_set_timing(pg_ctx* c, int enable) {

@@ -1,31 +1,33 @@
 // Device kernels of one evaluation: transition matrices, post-order pass,
-// root integration, pre-order pass fused with the gradient, and the
-// fixed-order reduction of per-tile gradient sums.
+// pre-order pass fused with the gradient, and the fixed-order reduction of
+// per-tile gradient sums together with the logL reduction.
 //
-// Data layout in HBM (pattern index fastest, so a group of 16 lanes that
-// handles 16 consecutive patterns reads one contiguous run per state):
-//   P     [branch][category][x][y]       x = parent state, y = child state
-//   msg   [internal node - N][category][state][pattern]   message P_k p~_k
-//   qv    [internal node - N][category][state][pattern]   pre-order q~_k
-//   codes [tip][pattern]                 uint8 code of the tip observation
+// Data layout in HBM:
+//   P     [branch][category][x][y]      x = parent state, y = child state
+//   msg   [internal node - N][tile][state][TP]   message P_k p~_k
+//   qv    [internal node - N][tile][state][TP]   pre-order vector q~_k
+//   codes [tip][pattern]                uint8 code of the tip observation
+// A tile is TP consecutive patterns of one rate category (tile = l * n_pb +
+// pattern block), so one node's data for one tile is a single contiguous run.
 //
-// Work decomposition: a workgroup owns one tile = 16 consecutive patterns
-// of one rate category and walks the whole tree for it, level by level
-// (nodes of equal height are independent).  Its 256 threads are 16 node
-// slots x 16 pattern lanes; a barrier separates levels.  Tiles never
-// communicate, so there is no grid-wide synchronisation inside a pass.
+// Work decomposition: a workgroup owns one tile and walks the whole tree for
+// it, level by level (nodes of equal height are independent).  Its threads
+// are NS node slots x TP pattern lanes (NS = node_slots(M)); a barrier
+// separates levels.  Tiles
+// never communicate, so a pass needs no grid-wide synchronisation.
 //
-// Rescaling is per node, per pattern and per category, by an exact power of
-// two.  Categories therefore never mix inside the traversal: the per-site
-// likelihood L_s = sum_l w_l L_{s,l} is formed once at the root from each
-// category's scaled value and summed exponent, and the gradient uses
+// Rescaling is per node, pattern and category, by an exact power of two.
+// Categories never mix inside the traversal: the site likelihood
+// L_s = sum_l w_l L_{s,l} is formed from each category's scaled root value
+// and summed exponent, and the gradient uses
 //   d log L_s / dt_b = sum_l rho_{s,l} gamma_l (u^T Q m)/(u^T m),
 //   rho_{s,l} = w_l L_{s,l} / L_s,
-// which equals Eq. (GradientWithGamma) of Section 2.6 (u^T m = L_{s,l} up to
-// the category's own scale factor, which cancels in each ratio).
+// which equals Eq. (GradientWithGamma) of Section 2.6: u^T m is L_{s,l} up
+// to the category's own scale factor, which cancels in each ratio.
 #include "pg_internal.h"
 
 #include <climits>
+#include <utility>
 
 namespace pg {
 
@@ -45,34 +47,140 @@ __device__ inline double sum16(double v) {
     return v;
 }
 
-// Outgoing message of child c for category l and pattern s: the stored
-// P_c p~_c for an internal child, P_c times the tip indicator for a tip
-// (a column of P_c, or the sum of the allowed columns).
+__device__ inline size_t vec_off(const EvalArgs& a, int node, int tile, int M) {
+    return ((size_t)(node - a.n_tips) * a.n_tiles + tile) * (size_t)(M * TP);
+}
+
+// Small state spaces (M*M <= TP): a node slot is one 16-lane DPP row, and a
+// transition matrix is held one entry per lane (lane e holds P[e / M][e % M]),
+// loaded with a single coalesced access.  An entry is delivered to every lane
+// of the row by a row broadcast (v_mov_b64_dpp row_newbcast), so the matrix
+// is never replicated through the vector memory path.
+template <int M>
+struct RowMat {
+    static constexpr bool value = M * M <= TP;
+};
+
+template <int E>
+__device__ inline double row_bcast(double v) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x150 + E, 0xf, 0xf, false);
+}
+template <int E>
+__device__ inline float row_bcast(float v) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x150 + E, 0xf, 0xf, false);
+}
+
 template <int M, typename T>
-__device__ inline void child_message(const EvalArgs& a, int c, int l, int s, T out[M]) {
-    const T* P = static_cast<const T*>(a.P);
+__device__ inline T load_row_entry(const T* __restrict__ mat, int ps) {
+    return (ps < M * M) ? mat[ps] : T(0);
+}
+
+// All M*M entries of a row-distributed matrix in every lane of the row:
+// ent[e] = entry e (row-major).  Each broadcast runs with the whole row active.
+template <int M, typename T, int... E>
+__device__ inline void row_entries_impl(T pmine, T ent[M * M], std::integer_sequence<int, E...>) {
+    ((ent[E] = row_bcast<E>(pmine)), ...);
+}
+template <int M, typename T>
+__device__ inline void row_entries(T pmine, T ent[M * M]) {
+    row_entries_impl<M, T>(pmine, ent, std::make_integer_sequence<int, M * M>{});
+}
+
+// out = P p with P row-distributed (all lanes of the row must be active)
+template <int M, typename T>
+__device__ inline void row_matvec(T pmine, const T p[M], T out[M]) {
+    T ent[M * M];
+    row_entries<M, T>(pmine, ent);
+#pragma unroll
+    for (int x = 0; x < M; ++x) {
+        T acc = T(0);
+#pragma unroll
+        for (int y = 0; y < M; ++y) acc = fma(ent[x * M + y], p[y], acc);
+        out[x] = acc;
+    }
+}
+
+// out = P^T u with P row-distributed
+template <int M, typename T>
+__device__ inline void row_matvec_t(T pmine, const T u[M], T out[M]) {
+    T ent[M * M];
+    row_entries<M, T>(pmine, ent);
+#pragma unroll
+    for (int y = 0; y < M; ++y) {
+        T acc = T(0);
+#pragma unroll
+        for (int x = 0; x < M; ++x) acc = fma(ent[x * M + y], u[x], acc);
+        out[y] = acc;
+    }
+}
+
+// out[x] = sum_{y in mask} P[x][y] with P row-distributed
+template <int M, typename T>
+__device__ inline void row_masked_rows(T pmine, unsigned long long mask, T out[M]) {
+    T ent[M * M];
+    row_entries<M, T>(pmine, ent);
+#pragma unroll
+    for (int x = 0; x < M; ++x) {
+        T acc = T(0);
+#pragma unroll
+        for (int y = 0; y < M; ++y) acc += ((mask >> y) & 1ull) ? ent[x * M + y] : T(0);
+        out[x] = acc;
+    }
+}
+
+// Q[e] and pi[x]: from the kernel arguments for small M, else from memory
+template <int M>
+__device__ inline double qentry(const EvalArgs& a, int e) {
+    if constexpr (M * M <= 16) return a.Qs[e];
+    else return a.Q64[e];
+}
+template <int M>
+__device__ inline double pientry(const EvalArgs& a, int x) {
+    if constexpr (M <= 4) return a.pis[x];
+    else return a.pi64[x];
+}
+
+__device__ inline unsigned long long tip_mask(const EvalArgs& a, unsigned code, int M) {
+    if (code < (unsigned)M) return 1ull << code;
+    if (code == 255u) return ~0ull;
+    return a.masks[code];
+}
+
+// Outgoing message of child c for category l, pattern s: the stored
+// P_c p~_c of an internal child; for a tip, P_c times the tip indicator
+// (Section 2.1): the column of the observed state, or the sum of the allowed
+// columns.  For small M the whole matrix is loaded independently of the
+// tip code and the column is selected in registers, so no load waits on
+// another.
+template <int M, typename T>
+__device__ inline void child_message(const EvalArgs& a, int c, int l, int tile, int s, int ps,
+                                     T out[M]) {
     if (c < a.n_tips) {
-        const T* Pc = P + ((size_t)c * a.K + l) * M * M;
+        const T* Pc = static_cast<const T*>(a.P) + ((size_t)c * a.K + l) * M * M;
         const unsigned code = a.codes[(size_t)c * a.S_pad + s];
-        if (code < (unsigned)M) {
-#pragma unroll
-            for (int x = 0; x < M; ++x) out[x] = Pc[x * M + code];
+        if constexpr (RowMat<M>::value) {
+            const T pmine = load_row_entry<M, T>(Pc, ps);
+            const unsigned long long mask = tip_mask(a, code, M);
+            row_masked_rows<M, T>(pmine, mask, out);
         } else {
-            const unsigned long long mask = a.masks[code];
+            if (code < (unsigned)M) {
 #pragma unroll
-            for (int x = 0; x < M; ++x) {
-                T acc = T(0);
+                for (int x = 0; x < M; ++x) out[x] = Pc[x * M + code];
+            } else {
+                const unsigned long long mask = a.masks[code];
 #pragma unroll
-                for (int y = 0; y < M; ++y)
-                    if ((mask >> y) & 1ull) acc += Pc[x * M + y];
-                out[x] = acc;
+                for (int x = 0; x < M; ++x) {
+                    T acc = T(0);
+                    for (int y = 0; y < M; ++y)
+                        if ((mask >> y) & 1ull) acc += Pc[x * M + y];
+                    out[x] = acc;
+                }
             }
         }
     } else {
-        const T* src = static_cast<const T*>(a.msg) +
-                       ((size_t)(c - a.n_tips) * a.K + l) * M * a.S_pad + s;
+        const T* src = static_cast<const T*>(a.msg) + vec_off(a, c, tile, M) + ps;
 #pragma unroll
-        for (int x = 0; x < M; ++x) out[x] = src[(size_t)x * a.S_pad];
+        for (int x = 0; x < M; ++x) out[x] = src[x * TP];
     }
 }
 
@@ -85,6 +193,8 @@ __device__ inline void child_message(const EvalArgs& a, int c, int l, int s, T o
 //   F = A (I + A/2 (I + A/3 (... (I + A/DEG)))),      truncation < 1e-19,
 //   s times: F <- 2F + F F   ((I+F)^2 = I + 2F + F^2),
 //   P = I + F.
+// A branch length that is negative or not finite gives a NaN matrix, which
+// propagates to a NaN logL.
 
 constexpr int TAYLOR_DEG = 16;
 
@@ -109,10 +219,12 @@ __global__ void __launch_bounds__(256) pmat_reg_kernel(EvalArgs a) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.n_branches * a.K) return;
     const int b = idx / a.K, l = idx % a.K;
-    double tb = a.t[b];
+    const double tb = a.t[b];
+    T* out = static_cast<T*>(a.P) + ((size_t)b * a.K + l) * M * M;
     if (bad_length(tb)) {
-        atomicOr(a.status, 1);
-        tb = 0.0;
+#pragma unroll
+        for (int e = 0; e < M * M; ++e) out[e] = T(NAN);
+        return;
     }
     const double h = a.rates[l] * tb;
     double nrm = a.qnorm * h;
@@ -143,7 +255,6 @@ __global__ void __launch_bounds__(256) pmat_reg_kernel(EvalArgs a) {
 #pragma unroll
             for (int j = 0; j < M; ++j) W[i][j] = 2.0 * W[i][j] + G[i][j];
     }
-    T* out = static_cast<T*>(a.P) + ((size_t)b * a.K + l) * M * M;
 #pragma unroll
     for (int i = 0; i < M; ++i)
 #pragma unroll
@@ -156,10 +267,11 @@ __global__ void __launch_bounds__(256) pmat_lds_kernel(EvalArgs a) {
     __shared__ double A[M * M], G[M * M], W[M * M];
     const int idx = blockIdx.x;
     const int b = idx / a.K, l = idx % a.K;
-    double tb = a.t[b];
+    const double tb = a.t[b];
+    T* out = static_cast<T*>(a.P) + ((size_t)b * a.K + l) * M * M;
     if (bad_length(tb)) {
-        if (threadIdx.x == 0) atomicOr(a.status, 1);
-        tb = 0.0;
+        for (int e = threadIdx.x; e < M * M; e += blockDim.x) out[e] = T(NAN);
+        return;
     }
     const double h = a.rates[l] * tb;
     double nrm = a.qnorm * h;
@@ -202,7 +314,6 @@ __global__ void __launch_bounds__(256) pmat_lds_kernel(EvalArgs a) {
         for (int e = threadIdx.x; e < M * M; e += blockDim.x) W[e] = 2.0 * W[e] + G[e];
         __syncthreads();
     }
-    T* out = static_cast<T*>(a.P) + ((size_t)b * a.K + l) * M * M;
     for (int e = threadIdx.x; e < M * M; e += blockDim.x)
         out[e] = T(((e / M == e % M) ? 1.0 : 0.0) + W[e]);
 }
@@ -217,13 +328,12 @@ __global__ void __launch_bounds__(256) pmat_lds_kernel(EvalArgs a) {
 // and the summed exponents of the pattern's column.
 
 template <int M, typename T>
-__global__ void __launch_bounds__(WG) post_kernel(EvalArgs a) {
+__global__ void __launch_bounds__(node_slots(M) * TP) post_kernel(EvalArgs a) {
+    constexpr int NS = node_slots(M);
     const int tile = blockIdx.x;
     const int l = tile / a.n_pb, pb = tile % a.n_pb;
     const int ps = threadIdx.x % TP, ns = threadIdx.x / TP;
     const int s = pb * TP + ps;
-    const T* P = static_cast<const T*>(a.P);
-    T* msg = static_cast<T*>(a.msg);
     int esum = 0;
     for (int h = 0; h < a.n_levels; ++h) {
         const int beg = a.level_off[h], end = a.level_off[h + 1];
@@ -231,8 +341,8 @@ __global__ void __launch_bounds__(WG) post_kernel(EvalArgs a) {
             const int k = a.level_nodes[idx];
             const int2 ch = a.children[k];
             T mi[M], mj[M], p[M];
-            child_message<M, T>(a, ch.x, l, s, mi);
-            child_message<M, T>(a, ch.y, l, s, mj);
+            child_message<M, T>(a, ch.x, l, tile, s, ps, mi);
+            child_message<M, T>(a, ch.y, l, tile, s, ps, mj);
             T mx = T(0);
 #pragma unroll
             for (int x = 0; x < M; ++x) {
@@ -247,19 +357,26 @@ __global__ void __launch_bounds__(WG) post_kernel(EvalArgs a) {
             }
             esum += e;
             if (k != a.root) {
-                const T* Pk = P + ((size_t)k * a.K + l) * M * M;
-                T* out = msg + ((size_t)(k - a.n_tips) * a.K + l) * M * a.S_pad + s;
+                const T* Pk = static_cast<const T*>(a.P) + ((size_t)k * a.K + l) * M * M;
+                T* out = static_cast<T*>(a.msg) + vec_off(a, k, tile, M) + ps;
+                T mk[M];
+                if constexpr (RowMat<M>::value) {
+                    row_matvec<M, T>(load_row_entry<M, T>(Pk, ps), p, mk);
+                } else {
 #pragma unroll
-                for (int x = 0; x < M; ++x) {
-                    T acc = T(0);
+                    for (int x = 0; x < M; ++x) {
+                        T acc = T(0);
 #pragma unroll
-                    for (int y = 0; y < M; ++y) acc = fma(Pk[x * M + y], p[y], acc);
-                    out[(size_t)x * a.S_pad] = acc;
+                        for (int y = 0; y < M; ++y) acc = fma(Pk[x * M + y], p[y], acc);
+                        mk[x] = acc;
+                    }
                 }
+#pragma unroll
+                for (int x = 0; x < M; ++x) out[x * TP] = mk[x];
             } else {
                 double Lt = 0.0;
 #pragma unroll
-                for (int x = 0; x < M; ++x) Lt = fma(a.pi64[x], (double)p[x], Lt);
+                for (int x = 0; x < M; ++x) Lt = fma(pientry<M>(a, x), (double)p[x], Lt);
                 a.rootL[(size_t)l * a.S_pad + s] = Lt;
             }
         }
@@ -275,63 +392,70 @@ __global__ void __launch_bounds__(WG) post_kernel(EvalArgs a) {
     }
 }
 
-// ---------------------------------------------------------------- root
+// ---------------------------------------------------------------- per-site likelihood
 //
 // L_s = sum_l w_l L~_{s,l} 2^{E_{s,l}}  (Eq. discreteRateLikelihood), formed
-// relative to the largest exponent so nothing under- or overflows;
-// rho_{s,l} = w_l L_{s,l} / L_s; logL = sum_s w_s log L_s.  One workgroup,
-// fixed-order reduction.
+// relative to the largest exponent so nothing under- or overflows.
 
-constexpr int ROOT_THREADS = 1024;
+struct SiteLik {
+    double scaled;  // L_s 2^-emax
+    int emax;
+    bool nan;
+};
 
-__global__ void __launch_bounds__(ROOT_THREADS) root_kernel(EvalArgs a) {
+__device__ inline SiteLik site_likelihood(const EvalArgs& a, int s) {
+    SiteLik r{0.0, INT_MIN, false};
+    for (int l = 0; l < a.K; ++l) {
+        const double L = a.rootL[(size_t)l * a.S_pad + s];
+        if (isnan(L)) r.nan = true;
+        if (L > 0.0) r.emax = max(r.emax, a.rootE[(size_t)l * a.S_pad + s]);
+    }
+    if (r.emax != INT_MIN)
+        for (int l = 0; l < a.K; ++l) {
+            const double L = a.rootL[(size_t)l * a.S_pad + s];
+            if (L > 0.0) r.scaled += a.catw[l] * ldexp(L, a.rootE[(size_t)l * a.S_pad + s] - r.emax);
+        }
+    return r;
+}
+
+// logL = sum_s w_s log L_s by one block of NT threads, fixed order.
+constexpr int LOGL_THREADS = 256;
+
+template <int NT>
+__device__ void logl_block(const EvalArgs& a) {
     const double LN2 = 0.69314718055994530942;
     double acc = 0.0;
-    int zero = 0;
-    for (int s = threadIdx.x; s < a.S_pad; s += ROOT_THREADS) {
-        int emax = INT_MIN;
-        for (int l = 0; l < a.K; ++l)
-            if (a.rootL[(size_t)l * a.S_pad + s] > 0.0) emax = max(emax, a.rootE[(size_t)l * a.S_pad + s]);
-        double tot = 0.0;
-        if (emax != INT_MIN)
-            for (int l = 0; l < a.K; ++l) {
-                const double L = a.rootL[(size_t)l * a.S_pad + s];
-                if (L > 0.0) tot += a.catw[l] * ldexp(L, a.rootE[(size_t)l * a.S_pad + s] - emax);
-            }
+    int flag = 0;
+    for (int s = threadIdx.x; s < a.S_pad; s += NT) {
         const double w = a.weights[s];
-        if (tot > 0.0) {
-            for (int l = 0; l < a.K; ++l) {
-                const double L = a.rootL[(size_t)l * a.S_pad + s];
-                a.rho[(size_t)l * a.S_pad + s] =
-                    (L > 0.0) ? a.catw[l] * ldexp(L, a.rootE[(size_t)l * a.S_pad + s] - emax) / tot : 0.0;
-            }
-            if (w > 0.0) acc += w * (log(tot) + (double)emax * LN2);
-        } else {
-            for (int l = 0; l < a.K; ++l) a.rho[(size_t)l * a.S_pad + s] = 0.0;
-            if (w > 0.0) zero = 1;
+        const SiteLik r = site_likelihood(a, s);
+        if (r.nan) flag |= 1;
+        else if (r.scaled > 0.0) {
+            if (w > 0.0) acc += w * (log(r.scaled) + (double)r.emax * LN2);
+        } else if (w > 0.0) {
+            flag |= 2;
         }
     }
-    __shared__ double red[ROOT_THREADS];
-    __shared__ int zred[ROOT_THREADS];
+    __shared__ double red[NT];
+    __shared__ int fred[NT];
     red[threadIdx.x] = acc;
-    zred[threadIdx.x] = zero;
+    fred[threadIdx.x] = flag;
     __syncthreads();
-    for (int w = ROOT_THREADS / 2; w > 0; w >>= 1) {
+    for (int w = NT / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
             red[threadIdx.x] += red[threadIdx.x + w];
-            zred[threadIdx.x] |= zred[threadIdx.x + w];
+            fred[threadIdx.x] |= fred[threadIdx.x + w];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        if (zred[0]) {
-            atomicOr(a.status, 2);
-            a.logL[0] = -INFINITY;
-        } else {
-            a.logL[0] = red[0];
-        }
+        const int f = fred[0];
+        a.logL_out[0] = (f & 1) ? NAN : (f & 2) ? -INFINITY : red[0];
+        a.status[0] = (f & 1) ? 1 : (f & 2) ? 2 : 0;
     }
 }
+
+__global__ void __launch_bounds__(LOGL_THREADS) logl_kernel(EvalArgs a) { logl_block<LOGL_THREADS>(a); }
 
 // ---------------------------------------------------------------- pre-order pass + gradient
 //
@@ -345,7 +469,7 @@ __global__ void __launch_bounds__(ROOT_THREADS) root_kernel(EvalArgs a) {
 // u_a^T Q m_a.
 
 template <int M, typename T>
-__device__ inline void pre_child(const EvalArgs& a, int c, int l, int s, int tile, int ps, double coef,
+__device__ inline void pre_child(const EvalArgs& a, int c, int l, int tile, int ps, double coef,
                                  const T q[M], const T msib[M], const T mown[M]) {
     T u[M];
 #pragma unroll
@@ -355,7 +479,7 @@ __device__ inline void pre_child(const EvalArgs& a, int c, int l, int s, int til
     for (int x = 0; x < M; ++x) {
         T qm = T(0);
 #pragma unroll
-        for (int y = 0; y < M; ++y) qm = fma(T(a.Q64[x * M + y]), mown[y], qm);
+        for (int y = 0; y < M; ++y) qm = fma(T(qentry<M>(a, x * M + y)), mown[y], qm);
         num = fma(u[x], qm, num);
         den = fma(u[x], mown[x], den);
     }
@@ -365,29 +489,43 @@ __device__ inline void pre_child(const EvalArgs& a, int c, int l, int s, int til
     if (c >= a.n_tips) {
         const T* Pc = static_cast<const T*>(a.P) + ((size_t)c * a.K + l) * M * M;
         T qc[M];
+        if constexpr (RowMat<M>::value) {
+            row_matvec_t<M, T>(load_row_entry<M, T>(Pc, ps), u, qc);
+        } else {
+#pragma unroll
+            for (int y = 0; y < M; ++y) {
+                T acc = T(0);
+#pragma unroll
+                for (int x = 0; x < M; ++x) acc = fma(Pc[x * M + y], u[x], acc);
+                qc[y] = acc;
+            }
+        }
         T mx = T(0);
 #pragma unroll
-        for (int y = 0; y < M; ++y) {
-            T acc = T(0);
-#pragma unroll
-            for (int x = 0; x < M; ++x) acc = fma(Pc[x * M + y], u[x], acc);
-            qc[y] = acc;
-            mx = fmax(mx, acc);
-        }
+        for (int y = 0; y < M; ++y) mx = fmax(mx, qc[y]);
         const int e = (mx > T(0)) ? exp_of(mx) : 0;
-        T* out = static_cast<T*>(a.qv) + ((size_t)(c - a.n_tips) * a.K + l) * M * a.S_pad + s;
+        T* out = static_cast<T*>(a.qv) + vec_off(a, c, tile, M) + ps;
 #pragma unroll
-        for (int y = 0; y < M; ++y) out[(size_t)y * a.S_pad] = pow2_scale(qc[y], -e);
+        for (int y = 0; y < M; ++y) out[y * TP] = pow2_scale(qc[y], -e);
     }
 }
 
 template <int M, typename T>
-__global__ void __launch_bounds__(WG) pre_kernel(EvalArgs a) {
+__global__ void __launch_bounds__(node_slots(M) * TP) pre_kernel(EvalArgs a) {
+    constexpr int NS = node_slots(M);
     const int tile = blockIdx.x;
     const int l = tile / a.n_pb, pb = tile % a.n_pb;
     const int ps = threadIdx.x % TP, ns = threadIdx.x / TP;
     const int s = pb * TP + ps;
-    const double coef = a.weights[s] * a.rho[(size_t)l * a.S_pad + s] * a.rates[l];
+    // rho_{s,l} gamma_l w_s from the per-category root values
+    double coef = 0.0;
+    {
+        const SiteLik r = site_likelihood(a, s);
+        const double L = a.rootL[(size_t)l * a.S_pad + s];
+        if (!r.nan && r.scaled > 0.0 && L > 0.0)
+            coef = a.weights[s] * a.rates[l] *
+                   (a.catw[l] * ldexp(L, a.rootE[(size_t)l * a.S_pad + s] - r.emax) / r.scaled);
+    }
     for (int h = a.n_levels - 1; h >= 0; --h) {
         const int beg = a.level_off[h], end = a.level_off[h + 1];
         for (int idx = beg + ns; idx < end; idx += NS) {
@@ -396,17 +534,16 @@ __global__ void __launch_bounds__(WG) pre_kernel(EvalArgs a) {
             T q[M], mi[M], mj[M];
             if (k == a.root) {
 #pragma unroll
-                for (int x = 0; x < M; ++x) q[x] = T(a.pi64[x]);
+                for (int x = 0; x < M; ++x) q[x] = T(pientry<M>(a, x));
             } else {
-                const T* src = static_cast<const T*>(a.qv) +
-                               ((size_t)(k - a.n_tips) * a.K + l) * M * a.S_pad + s;
+                const T* src = static_cast<const T*>(a.qv) + vec_off(a, k, tile, M) + ps;
 #pragma unroll
-                for (int x = 0; x < M; ++x) q[x] = src[(size_t)x * a.S_pad];
+                for (int x = 0; x < M; ++x) q[x] = src[x * TP];
             }
-            child_message<M, T>(a, ch.x, l, s, mi);
-            child_message<M, T>(a, ch.y, l, s, mj);
-            pre_child<M, T>(a, ch.x, l, s, tile, ps, coef, q, mj, mi);
-            pre_child<M, T>(a, ch.y, l, s, tile, ps, coef, q, mi, mj);
+            child_message<M, T>(a, ch.x, l, tile, s, ps, mi);
+            child_message<M, T>(a, ch.y, l, tile, s, ps, mj);
+            pre_child<M, T>(a, ch.x, l, tile, ps, coef, q, mj, mi);
+            pre_child<M, T>(a, ch.y, l, tile, ps, coef, q, mi, mj);
         }
         __syncthreads();
     }
@@ -414,14 +551,36 @@ __global__ void __launch_bounds__(WG) pre_kernel(EvalArgs a) {
 
 // ---------------------------------------------------------------- gradient reduction
 //
-// g_b = sum over tiles of the tile sums, in tile order (deterministic).
+// g_b = sum over tiles of the tile sums, in a fixed order: a block owns
+// GS_BRANCHES branches; its GS_SUB sub-lanes per branch sum interleaved tile
+// ranges in tile order, and the GS_SUB partial sums are combined by a fixed
+// binary tree.  One extra block computes logL.
 
-__global__ void __launch_bounds__(256) gsum_kernel(EvalArgs a) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= a.n_branches) return;
+constexpr int GS_THREADS = 1024;
+constexpr int GS_SUB = GS_THREADS / GS_BRANCHES;
+
+__global__ void __launch_bounds__(GS_THREADS) gsum_kernel(EvalArgs a) {
+    const int nbc = gsum_blocks(a.n_branches);
+    if ((int)blockIdx.x == nbc) {
+        logl_block<GS_THREADS>(a);
+        return;
+    }
+    const int B = a.n_branches;
+    const int bl = threadIdx.x % GS_BRANCHES, sl = threadIdx.x / GS_BRANCHES;
+    const int b = blockIdx.x * GS_BRANCHES + bl;
     double acc = 0.0;
-    for (int t = 0; t < a.n_tiles; ++t) acc += a.partial[(size_t)t * a.n_branches + b];
-    a.grad[b] = acc;
+    if (b < B) {
+        const double* src = a.partial + b;
+        for (int t = sl; t < a.n_tiles; t += GS_SUB) acc += src[(size_t)t * B];
+    }
+    __shared__ double red[GS_SUB][GS_BRANCHES];
+    red[sl][bl] = acc;
+    __syncthreads();
+    for (int w = GS_SUB / 2; w > 0; w >>= 1) {
+        if (sl < w) red[sl][bl] += red[sl + w][bl];
+        __syncthreads();
+    }
+    if (sl == 0 && b < B) a.grad_out[b] = red[0][bl];
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -441,13 +600,13 @@ static hipError_t pmat_launch(const EvalArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-#define PG_DISPATCH(FN, ...)                                                   \
-    do {                                                                       \
-        if (a.M == 4 && precision == PG_FP64) return FN<4, double>(__VA_ARGS__); \
-        if (a.M == 4 && precision == PG_FP32) return FN<4, float>(__VA_ARGS__);  \
+#define PG_DISPATCH(FN, ...)                                                     \
+    do {                                                                         \
+        if (a.M == 4 && precision == PG_FP64) return FN<4, double>(__VA_ARGS__);   \
+        if (a.M == 4 && precision == PG_FP32) return FN<4, float>(__VA_ARGS__);    \
         if (a.M == 20 && precision == PG_FP64) return FN<20, double>(__VA_ARGS__); \
         if (a.M == 20 && precision == PG_FP32) return FN<20, float>(__VA_ARGS__);  \
-        return hipErrorInvalidValue;                                           \
+        return hipErrorInvalidValue;                                             \
     } while (0)
 
 hipError_t launch_pmat(const EvalArgs& a, int precision, hipStream_t st) {
@@ -456,7 +615,7 @@ hipError_t launch_pmat(const EvalArgs& a, int precision, hipStream_t st) {
 
 template <int M, typename T>
 static hipError_t post_launch(const EvalArgs& a, hipStream_t st) {
-    post_kernel<M, T><<<a.n_tiles, WG, 0, st>>>(a);
+    post_kernel<M, T><<<a.n_tiles, node_slots(M) * TP, 0, st>>>(a);
     return hipGetLastError();
 }
 
@@ -464,14 +623,14 @@ hipError_t launch_post(const EvalArgs& a, int precision, hipStream_t st) {
     PG_DISPATCH(post_launch, a, st);
 }
 
-hipError_t launch_root(const EvalArgs& a, hipStream_t st) {
-    root_kernel<<<1, ROOT_THREADS, 0, st>>>(a);
+hipError_t launch_logl(const EvalArgs& a, hipStream_t st) {
+    logl_kernel<<<1, LOGL_THREADS, 0, st>>>(a);
     return hipGetLastError();
 }
 
 template <int M, typename T>
 static hipError_t pre_launch(const EvalArgs& a, hipStream_t st) {
-    pre_kernel<M, T><<<a.n_tiles, WG, 0, st>>>(a);
+    pre_kernel<M, T><<<a.n_tiles, node_slots(M) * TP, 0, st>>>(a);
     return hipGetLastError();
 }
 
@@ -480,11 +639,8 @@ hipError_t launch_pre(const EvalArgs& a, int precision, hipStream_t st) {
 }
 
 hipError_t launch_gsum(const EvalArgs& a, hipStream_t st) {
-    gsum_kernel<<<(a.n_branches + 255) / 256, 256, 0, st>>>(a);
+    gsum_kernel<<<gsum_blocks(a.n_branches) + 1, GS_THREADS, 0, st>>>(a);
     return hipGetLastError();
 }
-
-hipError_t launch_hess(const EvalArgs&, int, hipStream_t) { return hipErrorInvalidValue; }
-hipError_t launch_hsum(const EvalArgs&, hipStream_t) { return hipErrorInvalidValue; }
 
 }  // namespace pg

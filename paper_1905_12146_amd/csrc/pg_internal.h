@@ -13,21 +13,29 @@
 namespace pg {
 
 // Patterns per tile: one tile is TP consecutive patterns of one rate
-// category; 16 doubles (or floats) per state form one 128 B (64 B) run.
+// category.  A node's data for one tile, M states x TP patterns, is one
+// contiguous run (512 B for FP64 and M = 4).
 constexpr int TP = 16;
-// Threads per workgroup of the traversal kernels: NS node slots x TP lanes.
-constexpr int WG = 256;
-constexpr int NS = WG / TP;
+// Node slots per workgroup of the traversal kernels (each slot is TP lanes):
+// the workgroup has node_slots(M) * TP threads.
+__host__ __device__ constexpr int node_slots(int M) { return M <= 8 ? 32 : 16; }
+// Branches per block of the gradient reduction.
+constexpr int GS_BRANCHES = 16;
+__host__ __device__ inline int gsum_blocks(int n_branches) {
+    return (n_branches + GS_BRANCHES - 1) / GS_BRANCHES;
+}
 
 // Everything a kernel of one evaluation needs, passed by value.
 struct EvalArgs {
     int n_tips, n_nodes, n_branches, root;
     int K, M, S, S_pad, n_pb, n_tiles, n_levels;
     double qnorm;                      // max_x sum_y |Q[x][y]|
-    const double* t;                   // [B] branch lengths
+    double Qs[16];                     // Q by value when M*M <= 16 (kernel arguments
+    double pis[4];                     // are uniform: read through the scalar cache)
+    const double* t;                   // [B] branch lengths (device)
     void* P;                           // [B][K][M][M] storage type
-    void* msg;                         // [N-1][K][M][S_pad] outgoing messages P_k p_k
-    void* qv;                          // [N-1][K][M][S_pad] pre-order vectors q_k
+    void* msg;                         // [N-1][n_tiles][M][TP] outgoing messages P_k p~_k
+    void* qv;                          // [N-1][n_tiles][M][TP] pre-order vectors q~_k
     const uint8_t* codes;              // [N][S_pad] tip codes
     const unsigned long long* masks;   // [256] code -> state mask
     const int* level_off;              // [H+1] offsets into level_nodes
@@ -41,13 +49,13 @@ struct EvalArgs {
     const double* weights;             // [S_pad], 0 on padding
     double* rootL;                     // [K][S_pad] pi^T p~_root per category
     int* rootE;                        // [K][S_pad] summed scale exponents
-    double* rho;                       // [K][S_pad] posterior category weights
     double* partial;                   // [n_tiles][B] tile gradient sums
     double* partial2;                  // [n_pb][B] tile Hessian sums
-    double* grad;                      // [B]
-    double* hess;                      // [B]
-    double* logL;                      // [1]
-    int* status;                       // [1] 0 ok, 1 bad t, 2 zero likelihood
+    double* grad_out;                  // [B] gradient destination
+    double* hess_out;                  // [B] Hessian-diagonal destination
+    double* logL_out;                  // [1] logL destination
+    int* status;                       // [1] written by each logL reduction: 0 ok,
+                                       //     1 NaN (bad length), 2 zero likelihood
 };
 
 enum Precision { FP64 = PG_FP64, FP32 = PG_FP32 };
@@ -56,10 +64,9 @@ enum Precision { FP64 = PG_FP64, FP32 = PG_FP32 };
 bool kernel_supported(int M, int precision);
 hipError_t launch_pmat(const EvalArgs& a, int precision, hipStream_t s);
 hipError_t launch_post(const EvalArgs& a, int precision, hipStream_t s);
-hipError_t launch_root(const EvalArgs& a, hipStream_t s);
+hipError_t launch_logl(const EvalArgs& a, hipStream_t s);
 hipError_t launch_pre(const EvalArgs& a, int precision, hipStream_t s);
 hipError_t launch_gsum(const EvalArgs& a, hipStream_t s);
-hipError_t launch_hess(const EvalArgs& a, int precision, hipStream_t s);
-hipError_t launch_hsum(const EvalArgs& a, hipStream_t s);
+
 
 }  // namespace pg

@@ -146,7 +146,7 @@ def main():
     avg_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in times.items()}
     bm = byte_model(N, S, m, K, es)
     dom = max(("post", "pre"), key=lambda k: avg_ms[k])
-    achieved = bm[dom] / (avg_ms[dom] * 1e-3) / 1e9
+    achieved = bm[dom] / (avg_ms[dom] * 1e-3) / 1e9 if avg_ms[dom] > 0 else 0.0
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "bytes_per_launch": bm[dom], "avg_us": round(avg_ms[dom] * 1e3, 2),

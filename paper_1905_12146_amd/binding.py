@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libphylograd.so")
+# PHYLOGRAD_LIB overrides the in-tree library (e.g. a build with other flags)
+LIB_PATH = os.environ.get("PHYLOGRAD_LIB") or os.path.join(HERE, "libphylograd.so")
 
 PG_OK = 0
 PG_E_INVALID = -1

@@ -208,8 +208,7 @@ int upload(pg_ctx* c) {
     if ((r = ensure_buf(c, "codes", (size_t)N * c->S_pad))) return r;
     if ((r = ensure_buf(c, "masks", sizeof(unsigned long long) * 256))) return r;
     if ((r = ensure_buf(c, "level_off", sizeof(int) * c->level_off.size()))) return r;
-    if ((r = ensure_buf(c, "level_nodes", sizeof(int) * c->level_nodes.size()))) return r;
-    if ((r = ensure_buf(c, "children", sizeof(int2) * n_nodes))) return r;
+    if ((r = ensure_buf(c, "sched", sizeof(int4) * c->level_nodes.size()))) return r;
     if ((r = ensure_buf(c, "Q64", sizeof(double) * M * M))) return r;
     if ((r = ensure_buf(c, "Q2_64", sizeof(double) * M * M))) return r;
     if ((r = ensure_buf(c, "pi64", sizeof(double) * M))) return r;
@@ -220,6 +219,8 @@ int upload(pg_ctx* c) {
     if ((r = ensure_buf(c, "rootE", sizeof(int) * K * c->S_pad))) return r;
     if ((r = ensure_buf(c, "partial", sizeof(double) * (size_t)n_tiles * B))) return r;
     if ((r = ensure_buf(c, "partial2", sizeof(double) * (size_t)n_pb * B))) return r;
+    if ((r = ensure_buf(c, "logl_part", sizeof(double) * (size_t)n_pb))) return r;
+    if ((r = ensure_buf(c, "flag_part", sizeof(int) * (size_t)n_pb))) return r;
     if ((r = ensure_buf(c, "grad", sizeof(double) * B))) return r;
     if ((r = ensure_buf(c, "hess", sizeof(double) * B))) return r;
     if ((r = ensure_buf(c, "logL", sizeof(double) * 2))) return r;
@@ -229,12 +230,15 @@ int upload(pg_ctx* c) {
     auto put = [&](const char* name, const void* src, size_t bytes) {
         return hipMemcpyAsync(c->bufs[name].ptr, src, bytes, hipMemcpyHostToDevice, st);
     };
-    std::vector<int2> ch(c->children);
+    std::vector<int4> sched(c->level_nodes.size());
+    for (size_t i = 0; i < sched.size(); ++i) {
+        const int k = c->level_nodes[i];
+        sched[i] = make_int4(k, c->children[k].x, c->children[k].y, 0);
+    }
     PG_HIP(c, put("codes", c->codes.data(), c->codes.size()));
     PG_HIP(c, put("masks", c->masks.data(), sizeof(unsigned long long) * 256));
     PG_HIP(c, put("level_off", c->level_off.data(), sizeof(int) * c->level_off.size()));
-    PG_HIP(c, put("level_nodes", c->level_nodes.data(), sizeof(int) * c->level_nodes.size()));
-    PG_HIP(c, put("children", ch.data(), sizeof(int2) * n_nodes));
+    PG_HIP(c, put("sched", sched.data(), sizeof(int4) * sched.size()));
     PG_HIP(c, put("Q64", c->Q.data(), sizeof(double) * M * M));
     PG_HIP(c, put("Q2_64", c->Q2.data(), sizeof(double) * M * M));
     PG_HIP(c, put("pi64", c->pi.data(), sizeof(double) * M));
@@ -267,8 +271,8 @@ int upload(pg_ctx* c) {
     a.codes = buf<uint8_t>(c, "codes");
     a.masks = buf<unsigned long long>(c, "masks");
     a.level_off = buf<int>(c, "level_off");
-    a.level_nodes = buf<int>(c, "level_nodes");
-    a.children = buf<int2>(c, "children");
+    a.sched = buf<int4>(c, "sched");
+    a.sched_lds = (sizeof(int4) * (size_t)(N - 1) <= (size_t)SCHED_LDS_MAX) ? 1 : 0;
     a.Q64 = buf<double>(c, "Q64");
     a.Q2_64 = buf<double>(c, "Q2_64");
     a.pi64 = buf<double>(c, "pi64");
@@ -279,6 +283,8 @@ int upload(pg_ctx* c) {
     a.rootE = buf<int>(c, "rootE");
     a.partial = buf<double>(c, "partial");
     a.partial2 = buf<double>(c, "partial2");
+    a.logl_part = buf<double>(c, "logl_part");
+    a.flag_part = buf<int>(c, "flag_part");
     a.grad_out = buf<double>(c, "grad");
     a.hess_out = buf<double>(c, "hess");
     a.logL_out = buf<double>(c, "logL");

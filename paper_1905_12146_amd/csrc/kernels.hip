@@ -61,13 +61,15 @@ struct RowMat {
     static constexpr bool value = M * M <= TP;
 };
 
+// row_newbcast always reads a valid lane, so bound_ctrl only spares the
+// compiler from initialising the destination.
 template <int E>
 __device__ inline double row_bcast(double v) {
-    return __builtin_amdgcn_update_dpp(v, v, 0x150 + E, 0xf, 0xf, false);
+    return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + E, 0xf, 0xf, true);
 }
 template <int E>
 __device__ inline float row_bcast(float v) {
-    return __builtin_amdgcn_update_dpp(v, v, 0x150 + E, 0xf, 0xf, false);
+    return __builtin_amdgcn_update_dpp(0.0f, v, 0x150 + E, 0xf, 0xf, true);
 }
 
 template <int M, typename T>
@@ -86,32 +88,31 @@ __device__ inline void row_entries(T pmine, T ent[M * M]) {
     row_entries_impl<M, T>(pmine, ent, std::make_integer_sequence<int, M * M>{});
 }
 
-// out = P p with P row-distributed (all lanes of the row must be active)
+// out = P p with P row-distributed (all lanes of the row must be active).
+// Entry e = x M + y is broadcast and consumed at once; for each x the sum
+// runs over y in increasing order.
+template <int M, typename T, int... E>
+__device__ inline void row_matvec_impl(T pmine, const T p[M], T out[M], std::integer_sequence<int, E...>) {
+#pragma unroll
+    for (int x = 0; x < M; ++x) out[x] = T(0);
+    ((out[E / M] = fma(row_bcast<E>(pmine), p[E % M], out[E / M])), ...);
+}
 template <int M, typename T>
 __device__ inline void row_matvec(T pmine, const T p[M], T out[M]) {
-    T ent[M * M];
-    row_entries<M, T>(pmine, ent);
-#pragma unroll
-    for (int x = 0; x < M; ++x) {
-        T acc = T(0);
-#pragma unroll
-        for (int y = 0; y < M; ++y) acc = fma(ent[x * M + y], p[y], acc);
-        out[x] = acc;
-    }
+    row_matvec_impl<M, T>(pmine, p, out, std::make_integer_sequence<int, M * M>{});
 }
 
-// out = P^T u with P row-distributed
+// out = P^T u with P row-distributed; for each y the sum runs over x in
+// increasing order.
+template <int M, typename T, int... E>
+__device__ inline void row_matvec_t_impl(T pmine, const T u[M], T out[M], std::integer_sequence<int, E...>) {
+#pragma unroll
+    for (int y = 0; y < M; ++y) out[y] = T(0);
+    ((out[E % M] = fma(row_bcast<E>(pmine), u[E / M], out[E % M])), ...);
+}
 template <int M, typename T>
 __device__ inline void row_matvec_t(T pmine, const T u[M], T out[M]) {
-    T ent[M * M];
-    row_entries<M, T>(pmine, ent);
-#pragma unroll
-    for (int y = 0; y < M; ++y) {
-        T acc = T(0);
-#pragma unroll
-        for (int x = 0; x < M; ++x) acc = fma(ent[x * M + y], u[x], acc);
-        out[y] = acc;
-    }
+    row_matvec_t_impl<M, T>(pmine, u, out, std::make_integer_sequence<int, M * M>{});
 }
 
 // out[x] = sum_{y in mask} P[x][y] with P row-distributed
@@ -149,25 +150,58 @@ __device__ inline unsigned long long tip_mask(const EvalArgs& a, unsigned code, 
 // Outgoing message of child c for category l, pattern s: the stored
 // P_c p~_c of an internal child; for a tip, P_c times the tip indicator
 // (Section 2.1): the column of the observed state, or the sum of the allowed
-// columns.  For small M the whole matrix is loaded independently of the
-// tip code and the column is selected in registers, so no load waits on
-// another.
+// columns.  Split in two so a node's loads can be issued one node ahead of
+// its arithmetic: child_load only issues loads, child_finish uses them.
 template <int M, typename T>
-__device__ inline void child_message(const EvalArgs& a, int c, int l, int tile, int s, int ps,
-                                     T out[M]) {
+struct ChildRaw {
+    T v[M];          // internal child: the message; tip (small M): v[0] = own matrix entry
+    unsigned code;   // tip code
+};
+
+template <int M, typename T>
+__device__ inline const T* pmat_of(const EvalArgs& a, int b, int l) {
+    return static_cast<const T*>(a.P) + ((size_t)b * a.K + l) * M * M;
+}
+
+template <int M, typename T>
+__device__ inline void child_load(const EvalArgs& a, int c, int l, int tile, int s, int ps,
+                                  ChildRaw<M, T>& r) {
     if (c < a.n_tips) {
-        const T* Pc = static_cast<const T*>(a.P) + ((size_t)c * a.K + l) * M * M;
-        const unsigned code = a.codes[(size_t)c * a.S_pad + s];
+        r.code = a.codes[(size_t)c * a.S_pad + s];
+        if constexpr (RowMat<M>::value) r.v[0] = load_row_entry<M, T>(pmat_of<M, T>(a, c, l), ps);
+    } else {
+        const T* src = static_cast<const T*>(a.msg) + vec_off(a, c, tile, M) + ps;
+#pragma unroll
+        for (int x = 0; x < M; ++x) r.v[x] = src[x * TP];
+    }
+}
+
+// All lanes of the node slot's row must be active (row broadcasts, shuffles).
+template <int M, typename T>
+__device__ inline void child_finish(const EvalArgs& a, int c, int l, const ChildRaw<M, T>& r, T out[M]) {
+    if (c < a.n_tips) {
+        const unsigned code = r.code;
         if constexpr (RowMat<M>::value) {
-            const T pmine = load_row_entry<M, T>(Pc, ps);
-            const unsigned long long mask = tip_mask(a, code, M);
-            row_masked_rows<M, T>(pmine, mask, out);
+            // observed state: column `code`, read from the lane holding entry
+            // (x, code); ambiguity codes (rare) sum the allowed columns
+            const int col = code < (unsigned)M ? (int)code : 0;
+#pragma unroll
+            for (int x = 0; x < M; ++x) out[x] = __shfl(r.v[0], x * M + col, TP);
+            if (__any(code >= (unsigned)M)) {
+                T amb[M];
+                row_masked_rows<M, T>(r.v[0], tip_mask(a, code, M), amb);
+                if (code >= (unsigned)M) {
+#pragma unroll
+                    for (int x = 0; x < M; ++x) out[x] = amb[x];
+                }
+            }
         } else {
+            const T* Pc = pmat_of<M, T>(a, c, l);
             if (code < (unsigned)M) {
 #pragma unroll
                 for (int x = 0; x < M; ++x) out[x] = Pc[x * M + code];
             } else {
-                const unsigned long long mask = a.masks[code];
+                const unsigned long long mask = tip_mask(a, code, M);
 #pragma unroll
                 for (int x = 0; x < M; ++x) {
                     T acc = T(0);
@@ -178,9 +212,22 @@ __device__ inline void child_message(const EvalArgs& a, int c, int l, int tile, 
             }
         }
     } else {
-        const T* src = static_cast<const T*>(a.msg) + vec_off(a, c, tile, M) + ps;
 #pragma unroll
-        for (int x = 0; x < M; ++x) out[x] = src[x * TP];
+        for (int x = 0; x < M; ++x) out[x] = r.v[x];
+    }
+}
+
+// Level-ordered schedule entry idx: {node, child 0, child 1, 0}, from LDS
+// when the schedule was staged there.
+__device__ inline int4 sched_at(const EvalArgs& a, const int4* lds, int idx) {
+    return a.sched_lds ? lds[idx] : a.sched[idx];
+}
+
+__device__ inline void stage_schedule(const EvalArgs& a, int4* lds) {
+    if (a.sched_lds) {
+        const int n = a.n_tips - 1;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = a.sched[i];
+        __syncthreads();
     }
 }
 
@@ -328,56 +375,94 @@ __global__ void __launch_bounds__(256) pmat_lds_kernel(EvalArgs a) {
 // and the summed exponents of the pattern's column.
 
 template <int M, typename T>
-__global__ void __launch_bounds__(node_slots(M) * TP) post_kernel(EvalArgs a) {
+__device__ inline void post_node(const EvalArgs& a, int4 nd, int l, int tile, int s, int ps,
+                                 const ChildRaw<M, T>& ri, const ChildRaw<M, T>& rj, T pk, int& esum) {
+    T mi[M], mj[M], p[M];
+    child_finish<M, T>(a, nd.y, l, ri, mi);
+    child_finish<M, T>(a, nd.z, l, rj, mj);
+    T mx = T(0);
+#pragma unroll
+    for (int x = 0; x < M; ++x) {
+        p[x] = mi[x] * mj[x];
+        mx = fmax(mx, p[x]);
+    }
+    int e = 0;
+    if (mx > T(0)) {
+        e = exp_of(mx);
+#pragma unroll
+        for (int x = 0; x < M; ++x) p[x] = pow2_scale(p[x], -e);
+    }
+    esum += e;
+    const int k = nd.x;
+    if (k != a.root) {
+        T mk[M];
+        if constexpr (RowMat<M>::value) {
+            row_matvec<M, T>(pk, p, mk);
+        } else {
+            const T* Pk = pmat_of<M, T>(a, k, l);
+#pragma unroll
+            for (int x = 0; x < M; ++x) {
+                T acc = T(0);
+#pragma unroll
+                for (int y = 0; y < M; ++y) acc = fma(Pk[x * M + y], p[y], acc);
+                mk[x] = acc;
+            }
+        }
+        T* out = static_cast<T*>(a.msg) + vec_off(a, k, tile, M) + ps;
+#pragma unroll
+        for (int x = 0; x < M; ++x) out[x * TP] = mk[x];
+    } else {
+        double Lt = 0.0;
+#pragma unroll
+        for (int x = 0; x < M; ++x) Lt = fma(pientry<M>(a, x), (double)p[x], Lt);
+        a.rootL[(size_t)l * a.S_pad + s] = Lt;
+    }
+}
+
+template <int M, typename T>
+__global__ void __launch_bounds__(node_slots(M) * TP) __attribute__((amdgpu_waves_per_eu(RowMat<M>::value ? 4 : 1)))
+post_kernel(EvalArgs a) {
     constexpr int NS = node_slots(M);
+    extern __shared__ int4 lds_sched[];
     const int tile = blockIdx.x;
     const int l = tile / a.n_pb, pb = tile % a.n_pb;
     const int ps = threadIdx.x % TP, ns = threadIdx.x / TP;
     const int s = pb * TP + ps;
+    stage_schedule(a, lds_sched);
     int esum = 0;
     for (int h = 0; h < a.n_levels; ++h) {
-        const int beg = a.level_off[h], end = a.level_off[h + 1];
-        for (int idx = beg + ns; idx < end; idx += NS) {
-            const int k = a.level_nodes[idx];
-            const int2 ch = a.children[k];
-            T mi[M], mj[M], p[M];
-            child_message<M, T>(a, ch.x, l, tile, s, ps, mi);
-            child_message<M, T>(a, ch.y, l, tile, s, ps, mj);
-            T mx = T(0);
-#pragma unroll
-            for (int x = 0; x < M; ++x) {
-                p[x] = mi[x] * mj[x];
-                mx = fmax(mx, p[x]);
-            }
-            int e = 0;
-            if (mx > T(0)) {
-                e = exp_of(mx);
-#pragma unroll
-                for (int x = 0; x < M; ++x) p[x] = pow2_scale(p[x], -e);
-            }
-            esum += e;
-            if (k != a.root) {
-                const T* Pk = static_cast<const T*>(a.P) + ((size_t)k * a.K + l) * M * M;
-                T* out = static_cast<T*>(a.msg) + vec_off(a, k, tile, M) + ps;
-                T mk[M];
-                if constexpr (RowMat<M>::value) {
-                    row_matvec<M, T>(load_row_entry<M, T>(Pk, ps), p, mk);
-                } else {
-#pragma unroll
-                    for (int x = 0; x < M; ++x) {
-                        T acc = T(0);
-#pragma unroll
-                        for (int y = 0; y < M; ++y) acc = fma(Pk[x * M + y], p[y], acc);
-                        mk[x] = acc;
-                    }
+        const int end = a.level_off[h + 1];
+        int idx = a.level_off[h] + ns;
+        if (idx < end) {
+            // software pipeline: the next node's loads are issued before this
+            // node's stores, so they never wait behind them
+            int4 nd = sched_at(a, lds_sched, idx);
+            ChildRaw<M, T> ri, rj;
+            T pk = T(0);
+            child_load<M, T>(a, nd.y, l, tile, s, ps, ri);
+            child_load<M, T>(a, nd.z, l, tile, s, ps, rj);
+            if constexpr (RowMat<M>::value)
+                if (nd.x != a.root) pk = load_row_entry<M, T>(pmat_of<M, T>(a, nd.x, l), ps);
+            while (true) {
+                const int nidx = idx + NS;
+                const bool more = nidx < end;
+                int4 nn = nd;
+                ChildRaw<M, T> ni, nj;
+                T npk = T(0);
+                if (more) {
+                    nn = sched_at(a, lds_sched, nidx);
+                    child_load<M, T>(a, nn.y, l, tile, s, ps, ni);
+                    child_load<M, T>(a, nn.z, l, tile, s, ps, nj);
+                    if constexpr (RowMat<M>::value)
+                        if (nn.x != a.root) npk = load_row_entry<M, T>(pmat_of<M, T>(a, nn.x, l), ps);
                 }
-#pragma unroll
-                for (int x = 0; x < M; ++x) out[x * TP] = mk[x];
-            } else {
-                double Lt = 0.0;
-#pragma unroll
-                for (int x = 0; x < M; ++x) Lt = fma(pientry<M>(a, x), (double)p[x], Lt);
-                a.rootL[(size_t)l * a.S_pad + s] = Lt;
+                post_node<M, T>(a, nd, l, tile, s, ps, ri, rj, pk, esum);
+                if (!more) break;
+                nd = nn;
+                ri = ni;
+                rj = nj;
+                pk = npk;
+                idx = nidx;
             }
         }
         __syncthreads();
@@ -418,23 +503,47 @@ __device__ inline SiteLik site_likelihood(const EvalArgs& a, int s) {
     return r;
 }
 
-// logL = sum_s w_s log L_s by one block of NT threads, fixed order.
-constexpr int LOGL_THREADS = 256;
+// logL = sum_s w_s log L_s in one fixed order, shared by every path:
+//   part[pb] = butterfly sum over the TP patterns of block pb (sum16),
+//   logL     = fixed reduction of part[0..n_pb) (finish_logl).
+// site_log_term gives one pattern's term and status flag.
+__device__ inline double site_log_term(const EvalArgs& a, int s, const SiteLik& r, int& flag) {
+    const double LN2 = 0.69314718055994530942;
+    const double w = a.weights[s];
+    flag = 0;
+    if (r.nan) { flag = 1; return 0.0; }
+    if (r.scaled > 0.0) return (w > 0.0) ? w * (log(r.scaled) + (double)r.emax * LN2) : 0.0;
+    if (w > 0.0) flag = 2;
+    return 0.0;
+}
+
+__device__ inline int or16(int v) {
+    v |= __shfl_xor(v, 1, 16);
+    v |= __shfl_xor(v, 2, 16);
+    v |= __shfl_xor(v, 4, 16);
+    v |= __shfl_xor(v, 8, 16);
+    return v;
+}
+
+// One 16-lane row computes part[pb] (all lanes of the row active).
+__device__ inline void logl_block_part(const EvalArgs& a, int pb, int ps, const SiteLik& r) {
+    int flag;
+    double v = site_log_term(a, pb * TP + ps, r, flag);
+    v = sum16(v);
+    flag = or16(flag);
+    if (ps == 0) {
+        a.logl_part[pb] = v;
+        a.flag_part[pb] = flag;
+    }
+}
 
 template <int NT>
-__device__ void logl_block(const EvalArgs& a) {
-    const double LN2 = 0.69314718055994530942;
+__device__ void finish_logl(const EvalArgs& a) {
     double acc = 0.0;
     int flag = 0;
-    for (int s = threadIdx.x; s < a.S_pad; s += NT) {
-        const double w = a.weights[s];
-        const SiteLik r = site_likelihood(a, s);
-        if (r.nan) flag |= 1;
-        else if (r.scaled > 0.0) {
-            if (w > 0.0) acc += w * (log(r.scaled) + (double)r.emax * LN2);
-        } else if (w > 0.0) {
-            flag |= 2;
-        }
+    for (int pb = threadIdx.x; pb < a.n_pb; pb += NT) {
+        acc += a.logl_part[pb];
+        flag |= a.flag_part[pb];
     }
     __shared__ double red[NT];
     __shared__ int fred[NT];
@@ -455,7 +564,17 @@ __device__ void logl_block(const EvalArgs& a) {
     }
 }
 
-__global__ void __launch_bounds__(LOGL_THREADS) logl_kernel(EvalArgs a) { logl_block<LOGL_THREADS>(a); }
+// Forward-only calls: one block forms every part, then finishes.
+constexpr int LOGL_THREADS = 1024;
+
+__global__ void __launch_bounds__(LOGL_THREADS) logl_kernel(EvalArgs a) {
+    const int ps = threadIdx.x % TP, row = threadIdx.x / TP;
+    for (int pb = row; pb < a.n_pb; pb += LOGL_THREADS / TP)
+        logl_block_part(a, pb, ps, site_likelihood(a, pb * TP + ps));
+    __threadfence_block();
+    __syncthreads();
+    finish_logl<LOGL_THREADS>(a);
+}
 
 // ---------------------------------------------------------------- pre-order pass + gradient
 //
@@ -470,7 +589,7 @@ __global__ void __launch_bounds__(LOGL_THREADS) logl_kernel(EvalArgs a) { logl_b
 
 template <int M, typename T>
 __device__ inline void pre_child(const EvalArgs& a, int c, int l, int tile, int ps, double coef,
-                                 const T q[M], const T msib[M], const T mown[M]) {
+                                 const T q[M], const T msib[M], const T mown[M], T pc) {
     T u[M];
 #pragma unroll
     for (int x = 0; x < M; ++x) u[x] = q[x] * msib[x];
@@ -487,11 +606,11 @@ __device__ inline void pre_child(const EvalArgs& a, int c, int l, int tile, int 
     term = sum16(term);
     if (ps == 0) a.partial[(size_t)tile * a.n_branches + c] = term;
     if (c >= a.n_tips) {
-        const T* Pc = static_cast<const T*>(a.P) + ((size_t)c * a.K + l) * M * M;
         T qc[M];
         if constexpr (RowMat<M>::value) {
-            row_matvec_t<M, T>(load_row_entry<M, T>(Pc, ps), u, qc);
+            row_matvec_t<M, T>(pc, u, qc);
         } else {
+            const T* Pc = pmat_of<M, T>(a, c, l);
 #pragma unroll
             for (int y = 0; y < M; ++y) {
                 T acc = T(0);
@@ -510,9 +629,67 @@ __device__ inline void pre_child(const EvalArgs& a, int c, int l, int tile, int 
     }
 }
 
+// Loads of one pre-order node: q of the node, both children's messages and,
+// for small M, the children's own matrix entries.
 template <int M, typename T>
-__global__ void __launch_bounds__(node_slots(M) * TP) pre_kernel(EvalArgs a) {
-    constexpr int NS = node_slots(M);
+struct PreRaw {
+    T q[M];
+    ChildRaw<M, T> ri, rj;
+    T pi_, pj_;
+};
+
+template <int M, typename T>
+__device__ inline void pre_load(const EvalArgs& a, int4 nd, int l, int tile, int s, int ps, PreRaw<M, T>& r) {
+    if (nd.x == a.root) {
+#pragma unroll
+        for (int x = 0; x < M; ++x) r.q[x] = T(pientry<M>(a, x));
+    } else {
+        const T* src = static_cast<const T*>(a.qv) + vec_off(a, nd.x, tile, M) + ps;
+#pragma unroll
+        for (int x = 0; x < M; ++x) r.q[x] = src[x * TP];
+    }
+    child_load<M, T>(a, nd.y, l, tile, s, ps, r.ri);
+    child_load<M, T>(a, nd.z, l, tile, s, ps, r.rj);
+    r.pi_ = r.pj_ = T(0);
+    if constexpr (RowMat<M>::value) {
+        if (nd.y >= a.n_tips) r.pi_ = load_row_entry<M, T>(pmat_of<M, T>(a, nd.y, l), ps);
+        if (nd.z >= a.n_tips) r.pj_ = load_row_entry<M, T>(pmat_of<M, T>(a, nd.z, l), ps);
+    }
+}
+
+template <int M, typename T>
+__device__ inline void pre_node(const EvalArgs& a, int4 nd, int l, int tile, int ps, double coef,
+                                const PreRaw<M, T>& r) {
+    T mi[M], mj[M];
+    child_finish<M, T>(a, nd.y, l, r.ri, mi);
+    child_finish<M, T>(a, nd.z, l, r.rj, mj);
+    // a tip child's own matrix entry travels in its raw message slot
+    const T pi_ = (nd.y < a.n_tips) ? r.ri.v[0] : r.pi_;
+    const T pj_ = (nd.z < a.n_tips) ? r.rj.v[0] : r.pj_;
+    pre_child<M, T>(a, nd.y, l, tile, ps, coef, r.q, mj, mi, pi_);
+    pre_child<M, T>(a, nd.z, l, tile, ps, coef, r.q, mi, mj, pj_);
+}
+
+#ifndef PG_PRE_NS64
+#define PG_PRE_NS64 16
+#endif
+#ifndef PG_PRE_WPE64
+#define PG_PRE_WPE64 1
+#endif
+template <typename T>
+__host__ __device__ constexpr int pre_slots(int M) {
+    return (M * M <= TP && sizeof(T) == 8) ? PG_PRE_NS64 : node_slots(M);
+}
+template <typename T>
+__host__ __device__ constexpr int pre_waves(int M) {
+    return M * M <= TP ? (sizeof(T) == 8 ? PG_PRE_WPE64 : 4) : 1;
+}
+
+template <int M, typename T>
+__global__ void __launch_bounds__(pre_slots<T>(M) * TP) __attribute__((amdgpu_waves_per_eu(pre_waves<T>(M))))
+pre_kernel(EvalArgs a) {
+    constexpr int NS = pre_slots<T>(M);
+    extern __shared__ int4 lds_sched[];
     const int tile = blockIdx.x;
     const int l = tile / a.n_pb, pb = tile % a.n_pb;
     const int ps = threadIdx.x % TP, ns = threadIdx.x / TP;
@@ -525,25 +702,32 @@ __global__ void __launch_bounds__(node_slots(M) * TP) pre_kernel(EvalArgs a) {
         if (!r.nan && r.scaled > 0.0 && L > 0.0)
             coef = a.weights[s] * a.rates[l] *
                    (a.catw[l] * ldexp(L, a.rootE[(size_t)l * a.S_pad + s] - r.emax) / r.scaled);
+        // the category-0 tile of each pattern block also forms its logL part
+        if (l == 0 && ns == 0) logl_block_part(a, pb, ps, r);
     }
+    stage_schedule(a, lds_sched);
     for (int h = a.n_levels - 1; h >= 0; --h) {
-        const int beg = a.level_off[h], end = a.level_off[h + 1];
-        for (int idx = beg + ns; idx < end; idx += NS) {
-            const int k = a.level_nodes[idx];
-            const int2 ch = a.children[k];
-            T q[M], mi[M], mj[M];
-            if (k == a.root) {
-#pragma unroll
-                for (int x = 0; x < M; ++x) q[x] = T(pientry<M>(a, x));
-            } else {
-                const T* src = static_cast<const T*>(a.qv) + vec_off(a, k, tile, M) + ps;
-#pragma unroll
-                for (int x = 0; x < M; ++x) q[x] = src[x * TP];
+        const int end = a.level_off[h + 1];
+        int idx = a.level_off[h] + ns;
+        if (idx < end) {
+            int4 nd = sched_at(a, lds_sched, idx);
+            PreRaw<M, T> cur;
+            pre_load<M, T>(a, nd, l, tile, s, ps, cur);
+            while (true) {
+                const int nidx = idx + NS;
+                const bool more = nidx < end;
+                int4 nn = nd;
+                PreRaw<M, T> nxt;
+                if (more) {
+                    nn = sched_at(a, lds_sched, nidx);
+                    pre_load<M, T>(a, nn, l, tile, s, ps, nxt);
+                }
+                pre_node<M, T>(a, nd, l, tile, ps, coef, cur);
+                if (!more) break;
+                nd = nn;
+                cur = nxt;
+                idx = nidx;
             }
-            child_message<M, T>(a, ch.x, l, tile, s, ps, mi);
-            child_message<M, T>(a, ch.y, l, tile, s, ps, mj);
-            pre_child<M, T>(a, ch.x, l, tile, ps, coef, q, mj, mi);
-            pre_child<M, T>(a, ch.y, l, tile, ps, coef, q, mi, mj);
         }
         __syncthreads();
     }
@@ -562,16 +746,29 @@ constexpr int GS_SUB = GS_THREADS / GS_BRANCHES;
 __global__ void __launch_bounds__(GS_THREADS) gsum_kernel(EvalArgs a) {
     const int nbc = gsum_blocks(a.n_branches);
     if ((int)blockIdx.x == nbc) {
-        logl_block<GS_THREADS>(a);
+        finish_logl<GS_THREADS>(a);
         return;
     }
     const int B = a.n_branches;
     const int bl = threadIdx.x % GS_BRANCHES, sl = threadIdx.x / GS_BRANCHES;
     const int b = blockIdx.x * GS_BRANCHES + bl;
+    // tile sums t = sl, sl + GS_SUB, ... added in increasing t; a chunk of
+    // GS_UNROLL loads is issued before any of it is added (out-of-range
+    // entries are +0.0, which leaves the sum unchanged)
+    constexpr int GS_UNROLL = 8;
     double acc = 0.0;
     if (b < B) {
         const double* src = a.partial + b;
-        for (int t = sl; t < a.n_tiles; t += GS_SUB) acc += src[(size_t)t * B];
+        for (int t0 = sl; t0 < a.n_tiles; t0 += GS_UNROLL * GS_SUB) {
+            double v[GS_UNROLL];
+#pragma unroll
+            for (int j = 0; j < GS_UNROLL; ++j) {
+                const int t = t0 + j * GS_SUB;
+                v[j] = (t < a.n_tiles) ? src[(size_t)t * B] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < GS_UNROLL; ++j) acc += v[j];
+        }
     }
     __shared__ double red[GS_SUB][GS_BRANCHES];
     red[sl][bl] = acc;
@@ -615,7 +812,7 @@ hipError_t launch_pmat(const EvalArgs& a, int precision, hipStream_t st) {
 
 template <int M, typename T>
 static hipError_t post_launch(const EvalArgs& a, hipStream_t st) {
-    post_kernel<M, T><<<a.n_tiles, node_slots(M) * TP, 0, st>>>(a);
+    post_kernel<M, T><<<a.n_tiles, node_slots(M) * TP, sched_lds_bytes(a), st>>>(a);
     return hipGetLastError();
 }
 
@@ -630,7 +827,7 @@ hipError_t launch_logl(const EvalArgs& a, hipStream_t st) {
 
 template <int M, typename T>
 static hipError_t pre_launch(const EvalArgs& a, hipStream_t st) {
-    pre_kernel<M, T><<<a.n_tiles, node_slots(M) * TP, 0, st>>>(a);
+    pre_kernel<M, T><<<a.n_tiles, pre_slots<T>(M) * TP, sched_lds_bytes(a), st>>>(a);
     return hipGetLastError();
 }
 

@@ -21,6 +21,9 @@ constexpr int TP = 16;
 __host__ __device__ constexpr int node_slots(int M) { return M <= 8 ? 32 : 16; }
 // Branches per block of the gradient reduction.
 constexpr int GS_BRANCHES = 16;
+// The schedule is staged in LDS when it fits this budget (bytes).
+constexpr int SCHED_LDS_MAX = 32768;
+
 __host__ __device__ inline int gsum_blocks(int n_branches) {
     return (n_branches + GS_BRANCHES - 1) / GS_BRANCHES;
 }
@@ -38,9 +41,10 @@ struct EvalArgs {
     void* qv;                          // [N-1][n_tiles][M][TP] pre-order vectors q~_k
     const uint8_t* codes;              // [N][S_pad] tip codes
     const unsigned long long* masks;   // [256] code -> state mask
-    const int* level_off;              // [H+1] offsets into level_nodes
-    const int* level_nodes;            // internal nodes grouped by height
-    const int2* children;              // [2N-1] children of internal nodes
+    const int* level_off;              // [H+1] offsets into sched, by level
+    const int4* sched;                 // [N-1] {node, child 0, child 1, 0}, internal
+                                       //       nodes grouped by height
+    int sched_lds;                     // 1: traversal kernels stage sched in LDS
     const double* Q64;                 // [M][M]
     const double* Q2_64;               // [M][M] Q*Q
     const double* pi64;                // [M]
@@ -50,6 +54,8 @@ struct EvalArgs {
     double* rootL;                     // [K][S_pad] pi^T p~_root per category
     int* rootE;                        // [K][S_pad] summed scale exponents
     double* partial;                   // [n_tiles][B] tile gradient sums
+    double* logl_part;                 // [n_pb] sum_s w_s log L_s of each pattern block
+    int* flag_part;                    // [n_pb] 1 NaN, 2 zero likelihood in the block
     double* partial2;                  // [n_pb][B] tile Hessian sums
     double* grad_out;                  // [B] gradient destination
     double* hess_out;                  // [B] Hessian-diagonal destination
@@ -62,6 +68,7 @@ enum Precision { FP64 = PG_FP64, FP32 = PG_FP32 };
 
 // Kernel launchers (kernels.hip).  Each returns a hipError_t from the launch.
 bool kernel_supported(int M, int precision);
+inline size_t sched_lds_bytes(const EvalArgs& a) { return a.sched_lds ? sizeof(int4) * (a.n_tips - 1) : 0; }
 hipError_t launch_pmat(const EvalArgs& a, int precision, hipStream_t s);
 hipError_t launch_post(const EvalArgs& a, int precision, hipStream_t s);
 hipError_t launch_logl(const EvalArgs& a, hipStream_t s);

@@ -83,6 +83,44 @@ def cpu_baseline(w, n_branches_sample):
                       f"({per_eval:.0f} s); host {cpu_model()}, os.cpu_count()={os.cpu_count()}"}
 
 
+def calibrate_copy():
+    """Copy 1 GiB device to device three times and print the copy rate.
+
+    Under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE this gives the counters'
+    reading for a known 1 GiB read and 1 GiB write per copy."""
+    import torch
+    x = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    times = []
+    for _ in range(3):
+        ev[0].record()
+        y.copy_(x)
+        ev[1].record()
+        torch.cuda.synchronize()
+        times.append(ev[0].elapsed_time(ev[1]))
+    best = min(times)
+    print(json.dumps({"copy_bytes": 2 * 2 ** 30, "best_ms": best,
+                      "GB_per_s": 2 * 2 ** 30 / (best * 1e-3) / 1e9}), flush=True)
+
+
+def traffic_record(kernel, precision):
+    """HBM bytes per launch measured with rocprofv3 counters for this kernel
+    source (profiles/traffic.json), or None if the source has changed."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_1905_12146_amd", "csrc", "kernels.hip")
+    try:
+        rec = json.load(open(path))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_hip_sha256") != digest:
+        return None
+    entry = rec.get("C2", {}).get(precision, {}).get(kernel)
+    return None if entry is None else entry["read_bytes"] + entry["write_bytes"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,7 +130,12 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=30)
     ap.add_argument("--cpu-branches", type=int, default=20,
                     help="branches of the CPU oracle sample (0 disables the CPU leg)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 1 GiB device buffer 3 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the pattern-sharded multi-GPU layout is a design, not built)", file=sys.stderr)
@@ -148,7 +191,8 @@ def main():
     dom = max(("post", "pre"), key=lambda k: avg_ms[k])
     achieved = bm[dom] / (avg_ms[dom] * 1e-3) / 1e9 if avg_ms[dom] > 0 else 0.0
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_record(dom, args.precision),
                 "bytes_per_launch": bm[dom], "avg_us": round(avg_ms[dom] * 1e3, 2),
                 "kernels_avg_us": {k: round(v * 1e3, 2) for k, v in avg_ms.items()},
                 "eval_bytes": bm["post"] + bm["pre"],

@@ -146,11 +146,12 @@ int pg_logL_and_grad_device(pg_ctx* ctx, const double* d_t, double* d_logL,
  * stream): PG_OK, PG_E_INVALID (bad t) or PG_E_ZERO_LIK. */
 int pg_status(pg_ctx* ctx);
 
-/* Kernel timing.  While enabled, each evaluation records HIP events around
- * every kernel on the context's stream and waits for them; pg_get_timing
- * writes, for each PG_K_* kernel, the summed milliseconds into ms[k] and
- * the number of launches into launches[k] (arrays of PG_K_COUNT entries;
- * either may be NULL), then resets the sums. */
+/* Kernel timing.  While enabled, each evaluation records a pair of HIP
+ * events around every kernel on the context's stream (no synchronisation
+ * between kernels).  pg_get_timing waits for the recorded events, writes,
+ * for each PG_K_* kernel, the summed milliseconds into ms[k] and the number
+ * of launches into launches[k] (arrays of PG_K_COUNT entries; either may be
+ * NULL), then resets the sums. */
 int pg_set_timing(pg_ctx* ctx, int enable);
 int pg_get_timing(pg_ctx* ctx, double* ms, int64_t* launches);
 

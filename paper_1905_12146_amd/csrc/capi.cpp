@@ -60,11 +60,15 @@ struct pg_ctx {
     std::map<std::string, DevBuf> bufs;
     EvalArgs args{};
 
-    // timing
+    // timing: event pairs recorded around kernels, read after the stream
+    // passes them (no synchronisation between kernels)
     bool timing = false;
     double ms[PG_K_COUNT] = {0};
     int64_t launches[PG_K_COUNT] = {0};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> ev_pool;
+    struct Pending { int kid; hipEvent_t a, b; };
+    std::vector<Pending> pending;
 };
 
 namespace {
@@ -294,19 +298,47 @@ int upload(pg_ctx* c) {
     return PG_OK;
 }
 
+hipEvent_t pool_event(pg_ctx* c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Wait for the recorded event pairs, add their durations, recycle them.
+int drain_timing(pg_ctx* c) {
+    for (auto& p : c->pending) {
+        PG_HIP(c, hipEventSynchronize(p.b));
+        float ms = 0.f;
+        PG_HIP(c, hipEventElapsedTime(&ms, p.a, p.b));
+        c->ms[p.kid] += ms;
+        c->launches[p.kid] += 1;
+        c->ev_pool.push_back(p.a);
+        c->ev_pool.push_back(p.b);
+    }
+    c->pending.clear();
+    return PG_OK;
+}
+
 // Launch one kernel, bracketed by events when timing is on.
 template <typename F>
 int timed(pg_ctx* c, int kid, F&& launch) {
-    if (c->timing) PG_HIP(c, hipEventRecord(c->ev0, c->stream));
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c->timing) {
+        a = pool_event(c);
+        b = pool_event(c);
+        if (!a || !b) return fail(c, PG_E_DEVICE, "hipEventCreate failed");
+        PG_HIP(c, hipEventRecord(a, c->stream));
+    }
     hipError_t e = launch();
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
     if (c->timing) {
-        PG_HIP(c, hipEventRecord(c->ev1, c->stream));
-        PG_HIP(c, hipEventSynchronize(c->ev1));
-        float ms = 0.f;
-        PG_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-        c->ms[kid] += ms;
-        c->launches[kid] += 1;
+        PG_HIP(c, hipEventRecord(b, c->stream));
+        c->pending.push_back({kid, a, b});
     }
     return PG_OK;
 }
@@ -354,6 +386,8 @@ int finish_host(pg_ctx* c, double* logL, double* grad) {
         PG_HIP(c, hipMemcpyAsync(grad, c->args.grad_out, sizeof(double) * c->args.n_branches,
                                  hipMemcpyDeviceToHost, c->stream));
     PG_HIP(c, hipStreamSynchronize(c->stream));
+    int r = drain_timing(c);
+    if (r) return r;
     return status_code(c, status);
 }
 
@@ -426,6 +460,11 @@ void pg_destroy(pg_ctx* c) {
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    for (auto& p : c->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
 }
@@ -683,6 +722,8 @@ int pg_set_timing(pg_ctx* c, int enable) {
 
 int pg_get_timing(pg_ctx* c, double* ms, int64_t* launches) {
     if (!c) return PG_E_INVALID;
+    int r = guarded(c, [&] { return drain_timing(c); });
+    if (r) return r;
     for (int k = 0; k < PG_K_COUNT; ++k) {
         if (ms) ms[k] = c->ms[k];
         if (launches) launches[k] = c->launches[k];

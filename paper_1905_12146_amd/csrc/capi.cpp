@@ -234,10 +234,27 @@ int upload(pg_ctx* c) {
     auto put = [&](const char* name, const void* src, size_t bytes) {
         return hipMemcpyAsync(c->bufs[name].ptr, src, bytes, hipMemcpyHostToDevice, st);
     };
+    // pre-order top region: levels from the root down while every level has
+    // at most TOP_LEVEL_MAX_NODES nodes and their q vectors fit TOP_LDS_MAX
+    const int H = (int)c->level_off.size() - 1;
+    const int top_cap = std::min<int>(255, TOP_LDS_MAX / (int)(es * M * TP));
+    int top_level = H, top_nodes = 0;
+    for (int h = H - 1; h >= 0; --h) {
+        const int n_h = c->level_off[h + 1] - c->level_off[h];
+        if (n_h > TOP_LEVEL_MAX_NODES || top_nodes + n_h > top_cap) break;
+        top_nodes += n_h;
+        top_level = h;
+    }
+    std::vector<int> region(n_nodes, 0);
+    {
+        int next = 1;
+        for (int i = c->level_off[top_level]; i < c->level_off[H]; ++i) region[c->level_nodes[i]] = next++;
+    }
     std::vector<int4> sched(c->level_nodes.size());
     for (size_t i = 0; i < sched.size(); ++i) {
         const int k = c->level_nodes[i];
-        sched[i] = make_int4(k, c->children[k].x, c->children[k].y, 0);
+        const int c0 = c->children[k].x, c1 = c->children[k].y;
+        sched[i] = make_int4(k, c0, c1, region[k] | (region[c0] << 8) | (region[c1] << 16));
     }
     PG_HIP(c, put("codes", c->codes.data(), c->codes.size()));
     PG_HIP(c, put("masks", c->masks.data(), sizeof(unsigned long long) * 256));
@@ -277,6 +294,8 @@ int upload(pg_ctx* c) {
     a.level_off = buf<int>(c, "level_off");
     a.sched = buf<int4>(c, "sched");
     a.sched_lds = (sizeof(int4) * (size_t)(N - 1) <= (size_t)SCHED_LDS_MAX) ? 1 : 0;
+    a.top_level = top_level;
+    a.top_nodes = top_nodes;
     a.Q64 = buf<double>(c, "Q64");
     a.Q2_64 = buf<double>(c, "Q2_64");
     a.pi64 = buf<double>(c, "pi64");

@@ -38,12 +38,23 @@ __device__ inline int exp_of(float x) { int e; (void)frexpf(x, &e); return e; }
 __device__ inline double pow2_scale(double x, int e) { return ldexp(x, e); }
 __device__ inline float pow2_scale(float x, int e) { return ldexpf(x, e); }
 
-// Sum over the 16 lanes of a node slot; every lane gets the same value.
+// Sum over the 16 lanes of a node slot (one DPP row).  Each step adds the
+// row rotated by 1, 2, 4, 8 lanes (v_mov_b32_dpp row_ror on both halves of
+// the double), so every lane ends with the full row sum; callers use lane 0's
+// value, whose association order is fixed.
+template <int N>
+__device__ inline double row_ror(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x120 + N, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x120 + N, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
 __device__ inline double sum16(double v) {
-    v += __shfl_xor(v, 1, 16);
-    v += __shfl_xor(v, 2, 16);
-    v += __shfl_xor(v, 4, 16);
-    v += __shfl_xor(v, 8, 16);
+    v += row_ror<1>(v);
+    v += row_ror<2>(v);
+    v += row_ror<4>(v);
+    v += row_ror<8>(v);
     return v;
 }
 
@@ -229,6 +240,31 @@ __device__ inline void stage_schedule(const EvalArgs& a, int4* lds) {
         for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = a.sched[i];
         __syncthreads();
     }
+}
+
+// Top region of the pre-order pass: the levels from a.top_level up to the
+// root hold at most one node per node slot; q of their nodes is kept in LDS
+// (one M x TP block per region node) and never written to HBM, and the
+// levels are separated by LDS-only barriers.  sched.w packs 1-based region
+// slots: bits 0-7 the node, 8-15 child 0, 16-23 child 1 (0 = outside).
+__device__ inline int rslot(int w, int which) { return (w >> (8 * which)) & 0xff; }
+
+template <typename T>
+__device__ inline T* top_buffer(const EvalArgs& a, int4* lds_sched) {
+    return reinterpret_cast<T*>(lds_sched + (a.sched_lds ? a.n_tips - 1 : 0));
+}
+
+template <int M, typename T>
+__device__ inline T* top_vec(T* top, int slot, int ps) {
+    return top + (size_t)(slot - 1) * (M * TP) + ps;
+}
+
+// LDS-only barrier: waits for this wave's LDS operations, not for its
+// outstanding global stores.
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // ---------------------------------------------------------------- transition matrices
@@ -518,10 +554,10 @@ __device__ inline double site_log_term(const EvalArgs& a, int s, const SiteLik& 
 }
 
 __device__ inline int or16(int v) {
-    v |= __shfl_xor(v, 1, 16);
-    v |= __shfl_xor(v, 2, 16);
-    v |= __shfl_xor(v, 4, 16);
-    v |= __shfl_xor(v, 8, 16);
+    v |= __builtin_amdgcn_mov_dpp(v, 0x121, 0xf, 0xf, false);
+    v |= __builtin_amdgcn_mov_dpp(v, 0x122, 0xf, 0xf, false);
+    v |= __builtin_amdgcn_mov_dpp(v, 0x124, 0xf, 0xf, false);
+    v |= __builtin_amdgcn_mov_dpp(v, 0x128, 0xf, 0xf, false);
     return v;
 }
 
@@ -589,7 +625,7 @@ __global__ void __launch_bounds__(LOGL_THREADS) logl_kernel(EvalArgs a) {
 
 template <int M, typename T>
 __device__ inline void pre_child(const EvalArgs& a, int c, int l, int tile, int ps, double coef,
-                                 const T q[M], const T msib[M], const T mown[M], T pc) {
+                                 const T q[M], const T msib[M], const T mown[M], T pc, T* lds_dst) {
     T u[M];
 #pragma unroll
     for (int x = 0; x < M; ++x) u[x] = q[x] * msib[x];
@@ -623,7 +659,7 @@ __device__ inline void pre_child(const EvalArgs& a, int c, int l, int tile, int 
 #pragma unroll
         for (int y = 0; y < M; ++y) mx = fmax(mx, qc[y]);
         const int e = (mx > T(0)) ? exp_of(mx) : 0;
-        T* out = static_cast<T*>(a.qv) + vec_off(a, c, tile, M) + ps;
+        T* out = lds_dst ? lds_dst : static_cast<T*>(a.qv) + vec_off(a, c, tile, M) + ps;
 #pragma unroll
         for (int y = 0; y < M; ++y) out[y * TP] = pow2_scale(qc[y], -e);
     }
@@ -638,9 +674,12 @@ struct PreRaw {
     T pi_, pj_;
 };
 
+// with_q = false leaves q to the caller (top region: LDS or pi)
 template <int M, typename T>
-__device__ inline void pre_load(const EvalArgs& a, int4 nd, int l, int tile, int s, int ps, PreRaw<M, T>& r) {
-    if (nd.x == a.root) {
+__device__ inline void pre_load(const EvalArgs& a, int4 nd, int l, int tile, int s, int ps, PreRaw<M, T>& r,
+                                bool with_q = true) {
+    if (!with_q) {
+    } else if (nd.x == a.root) {
 #pragma unroll
         for (int x = 0; x < M; ++x) r.q[x] = T(pientry<M>(a, x));
     } else {
@@ -657,17 +696,25 @@ __device__ inline void pre_load(const EvalArgs& a, int4 nd, int l, int tile, int
     }
 }
 
+// top == nullptr: q of internal children goes to HBM; otherwise children in
+// the top region keep q in LDS only (it is consumed inside the region)
 template <int M, typename T>
 __device__ inline void pre_node(const EvalArgs& a, int4 nd, int l, int tile, int ps, double coef,
-                                const PreRaw<M, T>& r) {
+                                const T q[M], const PreRaw<M, T>& r, T* top) {
     T mi[M], mj[M];
     child_finish<M, T>(a, nd.y, l, r.ri, mi);
     child_finish<M, T>(a, nd.z, l, r.rj, mj);
     // a tip child's own matrix entry travels in its raw message slot
     const T pi_ = (nd.y < a.n_tips) ? r.ri.v[0] : r.pi_;
     const T pj_ = (nd.z < a.n_tips) ? r.rj.v[0] : r.pj_;
-    pre_child<M, T>(a, nd.y, l, tile, ps, coef, r.q, mj, mi, pi_);
-    pre_child<M, T>(a, nd.z, l, tile, ps, coef, r.q, mi, mj, pj_);
+    T* di = nullptr;
+    T* dj = nullptr;
+    if (top) {
+        if (const int si = rslot(nd.w, 1)) di = top_vec<M, T>(top, si, ps);
+        if (const int sj = rslot(nd.w, 2)) dj = top_vec<M, T>(top, sj, ps);
+    }
+    pre_child<M, T>(a, nd.y, l, tile, ps, coef, q, mj, mi, pi_, di);
+    pre_child<M, T>(a, nd.z, l, tile, ps, coef, q, mi, mj, pj_, dj);
 }
 
 #ifndef PG_PRE_NS64
@@ -706,7 +753,52 @@ pre_kernel(EvalArgs a) {
         if (l == 0 && ns == 0) logl_block_part(a, pb, ps, r);
     }
     stage_schedule(a, lds_sched);
-    for (int h = a.n_levels - 1; h >= 0; --h) {
+    T* top = top_buffer<T>(a, lds_sched);
+    // top region first: each slot issues its next level's loads (children
+    // messages of the post-order pass) before the LDS-only barrier; the last
+    // region level ends with a full barrier so the q written to HBM for the
+    // levels below is visible
+    if (a.top_level < a.n_levels) {
+        int h = a.n_levels - 1;
+        int idx = a.level_off[h] + ns;
+        bool have = idx < a.level_off[h + 1];
+        int4 nd = make_int4(0, 0, 0, 0);
+        PreRaw<M, T> cur;
+        if (have) {
+            nd = sched_at(a, lds_sched, idx);
+            pre_load<M, T>(a, nd, l, tile, s, ps, cur, false);
+        }
+        for (; h >= a.top_level; --h) {
+            const int h2 = h - 1;
+            const int idx2 = (h2 >= a.top_level) ? a.level_off[h2] + ns : 0;
+            const bool have2 = h2 >= a.top_level && idx2 < a.level_off[h2 + 1];
+            int4 nd2 = make_int4(0, 0, 0, 0);
+            PreRaw<M, T> nxt;
+            if (have2) {
+                nd2 = sched_at(a, lds_sched, idx2);
+                pre_load<M, T>(a, nd2, l, tile, s, ps, nxt, false);
+            }
+            if (have) {
+                T q[M];
+                if (nd.x == a.root) {
+#pragma unroll
+                    for (int x = 0; x < M; ++x) q[x] = T(pientry<M>(a, x));
+                } else {
+                    const T* src = top_vec<M, T>(top, rslot(nd.w, 0), ps);
+#pragma unroll
+                    for (int x = 0; x < M; ++x) q[x] = src[x * TP];
+                }
+                pre_node<M, T>(a, nd, l, tile, ps, coef, q, cur, top);
+            }
+            if (h > a.top_level) lds_barrier();
+            else __syncthreads();
+            have = have2;
+            nd = nd2;
+            cur = nxt;
+        }
+    }
+    // wide levels: several nodes per slot, software-pipelined
+    for (int h = a.top_level - 1; h >= 0; --h) {
         const int end = a.level_off[h + 1];
         int idx = a.level_off[h] + ns;
         if (idx < end) {
@@ -722,7 +814,7 @@ pre_kernel(EvalArgs a) {
                     nn = sched_at(a, lds_sched, nidx);
                     pre_load<M, T>(a, nn, l, tile, s, ps, nxt);
                 }
-                pre_node<M, T>(a, nd, l, tile, ps, coef, cur);
+                pre_node<M, T>(a, nd, l, tile, ps, coef, cur.q, cur, nullptr);
                 if (!more) break;
                 nd = nn;
                 cur = nxt;
@@ -827,7 +919,7 @@ hipError_t launch_logl(const EvalArgs& a, hipStream_t st) {
 
 template <int M, typename T>
 static hipError_t pre_launch(const EvalArgs& a, hipStream_t st) {
-    pre_kernel<M, T><<<a.n_tiles, pre_slots<T>(M) * TP, sched_lds_bytes(a), st>>>(a);
+    pre_kernel<M, T><<<a.n_tiles, pre_slots<T>(M) * TP, sched_lds_bytes(a) + top_lds_bytes(a, sizeof(T)), st>>>(a);
     return hipGetLastError();
 }
 

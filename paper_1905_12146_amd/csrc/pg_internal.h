@@ -23,6 +23,10 @@ __host__ __device__ constexpr int node_slots(int M) { return M <= 8 ? 32 : 16; }
 constexpr int GS_BRANCHES = 16;
 // The schedule is staged in LDS when it fits this budget (bytes).
 constexpr int SCHED_LDS_MAX = 32768;
+// LDS budget for the pre-order top region's q vectors, and the largest
+// level it admits (one node per node slot).
+constexpr int TOP_LDS_MAX = 32768;
+constexpr int TOP_LEVEL_MAX_NODES = 16;
 
 __host__ __device__ inline int gsum_blocks(int n_branches) {
     return (n_branches + GS_BRANCHES - 1) / GS_BRANCHES;
@@ -45,6 +49,9 @@ struct EvalArgs {
     const int4* sched;                 // [N-1] {node, child 0, child 1, 0}, internal
                                        //       nodes grouped by height
     int sched_lds;                     // 1: traversal kernels stage sched in LDS
+    int top_level;                     // first level of the pre-order top region
+                                       // (n_levels: none)
+    int top_nodes;                     // nodes in the top region (LDS blocks)
     const double* Q64;                 // [M][M]
     const double* Q2_64;               // [M][M] Q*Q
     const double* pi64;                // [M]
@@ -69,6 +76,7 @@ enum Precision { FP64 = PG_FP64, FP32 = PG_FP32 };
 // Kernel launchers (kernels.hip).  Each returns a hipError_t from the launch.
 bool kernel_supported(int M, int precision);
 inline size_t sched_lds_bytes(const EvalArgs& a) { return a.sched_lds ? sizeof(int4) * (a.n_tips - 1) : 0; }
+inline size_t top_lds_bytes(const EvalArgs& a, size_t elem) { return elem * (size_t)a.top_nodes * a.M * TP; }
 hipError_t launch_pmat(const EvalArgs& a, int precision, hipStream_t s);
 hipError_t launch_post(const EvalArgs& a, int precision, hipStream_t s);
 hipError_t launch_logl(const EvalArgs& a, hipStream_t s);

@@ -69,7 +69,10 @@ def linear_partials(parent, t, Q, pi, rates, cat_weights, masks, weights):
 
 
 def linear_gradient(parent, t, Q, pi, rates, cat_weights, masks, weights):
-    """dict(logL, grad, abs_grad, hess, site_log_likelihoods) by the O(N) passes."""
+    """dict(logL, grad, abs_grad, hess, abs_hess, site_log_likelihoods) by the O(N) passes.
+
+    abs_hess[i] = sum_s w_s (|d2L_s/L_s| + (dL_s/L_s)^2) bounds |hess[i]| and
+    scales its tolerance the way abs_grad does for the gradient."""
     tree, model, tips, t, w = validate(parent, t, Q, pi, rates, cat_weights, masks, weights)
     P = transition_matrices(model.Q, model.rates, t)
     p, lsp, q, lsq = _passes(tree, model, tips, P)
@@ -79,7 +82,7 @@ def linear_gradient(parent, t, Q, pi, rates, cat_weights, masks, weights):
     logL = math.fsum(np.where(w > 0, w * logLs, 0.0).tolist())
     Q2 = model.Q @ model.Q
     B = tree.n_nodes - 1
-    grad, absg, hess = np.zeros(B), np.zeros(B), np.zeros(B)
+    grad, absg, hess, absh = np.zeros(B), np.zeros(B), np.zeros(B), np.zeros(B)
     g1 = model.rates * model.cat_weights
     g2 = model.rates ** 2 * model.cat_weights
     for i in range(B):
@@ -94,4 +97,5 @@ def linear_gradient(parent, t, Q, pi, rates, cat_weights, masks, weights):
         grad[i] = math.fsum((w * r1).tolist())
         absg[i] = math.fsum(np.abs(w * r1).tolist())
         hess[i] = math.fsum((w * (r2 - r1 * r1)).tolist())
-    return dict(logL=logL, grad=grad, abs_grad=absg, hess=hess, site_log_likelihoods=logLs)
+        absh[i] = math.fsum((w * (np.abs(r2) + r1 * r1)).tolist())
+    return dict(logL=logL, grad=grad, abs_grad=absg, hess=hess, abs_hess=absh, site_log_likelihoods=logLs)

@@ -222,7 +222,7 @@ int upload(pg_ctx* c) {
     if ((r = ensure_buf(c, "rootL", sizeof(double) * K * c->S_pad))) return r;
     if ((r = ensure_buf(c, "rootE", sizeof(int) * K * c->S_pad))) return r;
     if ((r = ensure_buf(c, "partial", sizeof(double) * (size_t)n_tiles * B))) return r;
-    if ((r = ensure_buf(c, "partial2", sizeof(double) * (size_t)n_pb * B))) return r;
+    if ((r = ensure_buf(c, "partial2", sizeof(double) * (size_t)n_tiles * B))) return r;
     if ((r = ensure_buf(c, "logl_part", sizeof(double) * (size_t)n_pb))) return r;
     if ((r = ensure_buf(c, "flag_part", sizeof(int) * (size_t)n_pb))) return r;
     if ((r = ensure_buf(c, "grad", sizeof(double) * B))) return r;
@@ -284,6 +284,7 @@ int upload(pg_ctx* c) {
     a.n_levels = (int)c->level_off.size() - 1;
     a.qnorm = c->qnorm;
     for (int e = 0; e < 16; ++e) a.Qs[e] = (e < M * M) ? c->Q[e] : 0.0;
+    for (int e = 0; e < 16; ++e) a.Q2s[e] = (e < M * M) ? c->Q2[e] : 0.0;
     for (int e = 0; e < 4; ++e) a.pis[e] = (e < M) ? c->pi[e] : 0.0;
     a.t = buf<double>(c, "t");
     a.P = c->bufs["P"].ptr;
@@ -306,6 +307,7 @@ int upload(pg_ctx* c) {
     a.rootE = buf<int>(c, "rootE");
     a.partial = buf<double>(c, "partial");
     a.partial2 = buf<double>(c, "partial2");
+    a.r1 = nullptr;  // allocated by the first Hessian call
     a.logl_part = buf<double>(c, "logl_part");
     a.flag_part = buf<int>(c, "flag_part");
     a.grad_out = buf<double>(c, "grad");
@@ -385,7 +387,7 @@ int enqueue_forward(pg_ctx* c, const EvalArgs& a, bool with_logl) {
 
 int enqueue_backward(pg_ctx* c, const EvalArgs& a) {
     int r;
-    if ((r = timed(c, PG_K_PRE, [&] { return launch_pre(a, c->precision, c->stream); }))) return r;
+    if ((r = timed(c, PG_K_PRE, [&] { return launch_pre(a, c->precision, c->stream, false); }))) return r;
     if ((r = timed(c, PG_K_GSUM, [&] { return launch_gsum(a, c->stream); }))) return r;
     return PG_OK;
 }
@@ -698,9 +700,23 @@ int pg_logL_and_grad(pg_ctx* c, const double* t, double* logL, double* grad) {
 
 int pg_hessian_diag(pg_ctx* c, double* grad, double* hess) {
     if (!c) return PG_E_INVALID;
-    (void)grad;
-    (void)hess;
-    return fail(c, PG_E_UNSUPPORTED, "Hessian diagonal not built yet");
+    if (!hess) return fail(c, PG_E_INVALID, "NULL hess");
+    if (!c->have_partials || c->dev_stale)
+        return fail(c, PG_E_STATE, "no resident partials: call pg_logL first");
+    return guarded(c, [&] {
+        PG_HIP(c, hipSetDevice(c->device));
+        EvalArgs& a = c->args;
+        int r;
+        if ((r = ensure_buf(c, "r1", sizeof(double) * (size_t)a.n_branches * a.K * a.S_pad))) return r;
+        a.r1 = buf<double>(c, "r1");
+        if ((r = timed(c, PG_K_PRE, [&] { return launch_pre(a, c->precision, c->stream, true); }))) return r;
+        if ((r = timed(c, PG_K_GSUM, [&] { return launch_gsum(a, c->stream); }))) return r;
+        if ((r = timed(c, PG_K_GSUM, [&] { return launch_hsum(a, c->stream); }))) return r;
+        PG_HIP(c, hipMemcpyAsync(hess, a.hess_out, sizeof(double) * a.n_branches, hipMemcpyDeviceToHost,
+                                 c->stream));
+        double logL = 0.0;
+        return finish_host(c, &logL, grad);
+    });
 }
 
 int pg_logL_and_grad_device(pg_ctx* c, const double* d_t, double* d_logL, double* d_grad) {

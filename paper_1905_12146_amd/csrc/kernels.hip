@@ -147,6 +147,11 @@ __device__ inline double qentry(const EvalArgs& a, int e) {
     else return a.Q64[e];
 }
 template <int M>
+__device__ inline double q2entry(const EvalArgs& a, int e) {
+    if constexpr (M * M <= 16) return a.Q2s[e];
+    else return a.Q2_64[e];
+}
+template <int M>
 __device__ inline double pientry(const EvalArgs& a, int x) {
     if constexpr (M <= 4) return a.pis[x];
     else return a.pi64[x];
@@ -623,13 +628,25 @@ __global__ void __launch_bounds__(LOGL_THREADS) logl_kernel(EvalArgs a) {
 // The numerator uses Q m_a = Q P_a p_a = P_a Q p_a, so q_a^T Q p_a is
 // u_a^T Q m_a.
 
-template <int M, typename T>
-__device__ inline void pre_child(const EvalArgs& a, int c, int l, int tile, int ps, double coef,
+// Per-lane coefficients of pattern s in category l:
+//   g = w_s rho_{s,l} gamma_l      (gradient)
+//   nw = rho_{s,l} gamma_l         (per-site gradient part, Hessian)
+//   h = w_s rho_{s,l} gamma_l^2    (second-derivative part, Hessian)
+struct Coef {
+    double g, nw, h;
+};
+
+// HESS adds, for Eq. (Hessian) of Section 2.7 per site:
+//   tile sum of w_s rho gamma^2 (u^T Q^2 m)/(u^T m)   -> partial2[tile][c]
+//   rho gamma (u^T Q m)/(u^T m) for every pattern     -> r1[c][l][s]
+// so d2 logL/dt_c^2 = sum partial2 - sum_s w_s (sum_l r1)^2.
+template <int M, typename T, bool HESS>
+__device__ inline void pre_child(const EvalArgs& a, int c, int l, int tile, int s, int ps, const Coef& cf,
                                  const T q[M], const T msib[M], const T mown[M], T pc, T* lds_dst) {
     T u[M];
 #pragma unroll
     for (int x = 0; x < M; ++x) u[x] = q[x] * msib[x];
-    T den = T(0), num = T(0);
+    T den = T(0), num = T(0), num2 = T(0);
 #pragma unroll
     for (int x = 0; x < M; ++x) {
         T qm = T(0);
@@ -637,10 +654,24 @@ __device__ inline void pre_child(const EvalArgs& a, int c, int l, int tile, int 
         for (int y = 0; y < M; ++y) qm = fma(T(qentry<M>(a, x * M + y)), mown[y], qm);
         num = fma(u[x], qm, num);
         den = fma(u[x], mown[x], den);
+        if constexpr (HESS) {
+            T q2m = T(0);
+#pragma unroll
+            for (int y = 0; y < M; ++y) q2m = fma(T(q2entry<M>(a, x * M + y)), mown[y], q2m);
+            num2 = fma(u[x], q2m, num2);
+        }
     }
-    double term = (coef > 0.0 && den > T(0)) ? coef * ((double)num / (double)den) : 0.0;
+    const double ratio = (den > T(0)) ? (double)num / (double)den : 0.0;
+    double term = (cf.g > 0.0) ? cf.g * ratio : 0.0;
     term = sum16(term);
     if (ps == 0) a.partial[(size_t)tile * a.n_branches + c] = term;
+    if constexpr (HESS) {
+        const double ratio2 = (den > T(0)) ? (double)num2 / (double)den : 0.0;
+        double term2 = (cf.h > 0.0) ? cf.h * ratio2 : 0.0;
+        term2 = sum16(term2);
+        if (ps == 0) a.partial2[(size_t)tile * a.n_branches + c] = term2;
+        a.r1[((size_t)c * a.K + l) * a.S_pad + s] = (cf.nw > 0.0) ? cf.nw * ratio : 0.0;
+    }
     if (c >= a.n_tips) {
         T qc[M];
         if constexpr (RowMat<M>::value) {
@@ -698,8 +729,8 @@ __device__ inline void pre_load(const EvalArgs& a, int4 nd, int l, int tile, int
 
 // top == nullptr: q of internal children goes to HBM; otherwise children in
 // the top region keep q in LDS only (it is consumed inside the region)
-template <int M, typename T>
-__device__ inline void pre_node(const EvalArgs& a, int4 nd, int l, int tile, int ps, double coef,
+template <int M, typename T, bool HESS>
+__device__ inline void pre_node(const EvalArgs& a, int4 nd, int l, int tile, int s, int ps, const Coef& cf,
                                 const T q[M], const PreRaw<M, T>& r, T* top) {
     T mi[M], mj[M];
     child_finish<M, T>(a, nd.y, l, r.ri, mi);
@@ -713,8 +744,8 @@ __device__ inline void pre_node(const EvalArgs& a, int4 nd, int l, int tile, int
         if (const int si = rslot(nd.w, 1)) di = top_vec<M, T>(top, si, ps);
         if (const int sj = rslot(nd.w, 2)) dj = top_vec<M, T>(top, sj, ps);
     }
-    pre_child<M, T>(a, nd.y, l, tile, ps, coef, q, mj, mi, pi_, di);
-    pre_child<M, T>(a, nd.z, l, tile, ps, coef, q, mi, mj, pj_, dj);
+    pre_child<M, T, HESS>(a, nd.y, l, tile, s, ps, cf, q, mj, mi, pi_, di);
+    pre_child<M, T, HESS>(a, nd.z, l, tile, s, ps, cf, q, mi, mj, pj_, dj);
 }
 
 #ifndef PG_PRE_NS64
@@ -732,7 +763,7 @@ __host__ __device__ constexpr int pre_waves(int M) {
     return M * M <= TP ? (sizeof(T) == 8 ? PG_PRE_WPE64 : 4) : 1;
 }
 
-template <int M, typename T>
+template <int M, typename T, bool HESS>
 __global__ void __launch_bounds__(pre_slots<T>(M) * TP) __attribute__((amdgpu_waves_per_eu(pre_waves<T>(M))))
 pre_kernel(EvalArgs a) {
     constexpr int NS = pre_slots<T>(M);
@@ -742,13 +773,16 @@ pre_kernel(EvalArgs a) {
     const int ps = threadIdx.x % TP, ns = threadIdx.x / TP;
     const int s = pb * TP + ps;
     // rho_{s,l} gamma_l w_s from the per-category root values
-    double coef = 0.0;
+    Coef cf{0.0, 0.0, 0.0};
     {
         const SiteLik r = site_likelihood(a, s);
         const double L = a.rootL[(size_t)l * a.S_pad + s];
-        if (!r.nan && r.scaled > 0.0 && L > 0.0)
-            coef = a.weights[s] * a.rates[l] *
-                   (a.catw[l] * ldexp(L, a.rootE[(size_t)l * a.S_pad + s] - r.emax) / r.scaled);
+        if (!r.nan && r.scaled > 0.0 && L > 0.0) {
+            const double rho = a.catw[l] * ldexp(L, a.rootE[(size_t)l * a.S_pad + s] - r.emax) / r.scaled;
+            cf.nw = rho * a.rates[l];
+            cf.g = a.weights[s] * cf.nw;
+            cf.h = cf.g * a.rates[l];
+        }
         // the category-0 tile of each pattern block also forms its logL part
         if (l == 0 && ns == 0) logl_block_part(a, pb, ps, r);
     }
@@ -788,7 +822,7 @@ pre_kernel(EvalArgs a) {
 #pragma unroll
                     for (int x = 0; x < M; ++x) q[x] = src[x * TP];
                 }
-                pre_node<M, T>(a, nd, l, tile, ps, coef, q, cur, top);
+                pre_node<M, T, HESS>(a, nd, l, tile, s, ps, cf, q, cur, top);
             }
             if (h > a.top_level) lds_barrier();
             else __syncthreads();
@@ -814,7 +848,7 @@ pre_kernel(EvalArgs a) {
                     nn = sched_at(a, lds_sched, nidx);
                     pre_load<M, T>(a, nn, l, tile, s, ps, nxt);
                 }
-                pre_node<M, T>(a, nd, l, tile, ps, coef, cur.q, cur, nullptr);
+                pre_node<M, T, HESS>(a, nd, l, tile, s, ps, cf, cur.q, cur, nullptr);
                 if (!more) break;
                 nd = nn;
                 cur = nxt;
@@ -918,13 +952,51 @@ hipError_t launch_logl(const EvalArgs& a, hipStream_t st) {
 }
 
 template <int M, typename T>
-static hipError_t pre_launch(const EvalArgs& a, hipStream_t st) {
-    pre_kernel<M, T><<<a.n_tiles, pre_slots<T>(M) * TP, sched_lds_bytes(a) + top_lds_bytes(a, sizeof(T)), st>>>(a);
+static hipError_t pre_launch(const EvalArgs& a, hipStream_t st, bool hess) {
+    const size_t lds = sched_lds_bytes(a) + top_lds_bytes(a, sizeof(T));
+    if (hess) pre_kernel<M, T, true><<<a.n_tiles, pre_slots<T>(M) * TP, lds, st>>>(a);
+    else pre_kernel<M, T, false><<<a.n_tiles, pre_slots<T>(M) * TP, lds, st>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_pre(const EvalArgs& a, int precision, hipStream_t st) {
-    PG_DISPATCH(pre_launch, a, st);
+hipError_t launch_pre(const EvalArgs& a, int precision, hipStream_t st, bool hess) {
+    PG_DISPATCH(pre_launch, a, st, hess);
+}
+
+// ---------------------------------------------------------------- Hessian reduction
+//
+// One block per branch b:
+//   d2 logL/dt_b^2 = sum_t partial2[t][b] - sum_s w_s (sum_l r1[b][l][s])^2,
+// both sums in a fixed order (strided per thread, then a fixed tree).
+constexpr int HS_THREADS = 256;
+
+__global__ void __launch_bounds__(HS_THREADS) hsum_kernel(EvalArgs a) {
+    const int b = blockIdx.x;
+    const int B = a.n_branches;
+    double sq = 0.0, p2 = 0.0;
+    for (int s = threadIdx.x; s < a.S_pad; s += HS_THREADS) {
+        double g = 0.0;
+        for (int l = 0; l < a.K; ++l) g += a.r1[((size_t)b * a.K + l) * a.S_pad + s];
+        sq += a.weights[s] * g * g;
+    }
+    for (int t = threadIdx.x; t < a.n_tiles; t += HS_THREADS) p2 += a.partial2[(size_t)t * B + b];
+    __shared__ double rs[HS_THREADS], rp[HS_THREADS];
+    rs[threadIdx.x] = sq;
+    rp[threadIdx.x] = p2;
+    __syncthreads();
+    for (int w = HS_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            rs[threadIdx.x] += rs[threadIdx.x + w];
+            rp[threadIdx.x] += rp[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.hess_out[b] = rp[0] - rs[0];
+}
+
+hipError_t launch_hsum(const EvalArgs& a, hipStream_t st) {
+    hsum_kernel<<<a.n_branches, HS_THREADS, 0, st>>>(a);
+    return hipGetLastError();
 }
 
 hipError_t launch_gsum(const EvalArgs& a, hipStream_t st) {

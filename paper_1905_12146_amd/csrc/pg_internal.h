@@ -39,6 +39,7 @@ struct EvalArgs {
     double qnorm;                      // max_x sum_y |Q[x][y]|
     double Qs[16];                     // Q by value when M*M <= 16 (kernel arguments
     double pis[4];                     // are uniform: read through the scalar cache)
+    double Q2s[16];                    // Q*Q by value when M*M <= 16
     const double* t;                   // [B] branch lengths (device)
     void* P;                           // [B][K][M][M] storage type
     void* msg;                         // [N-1][n_tiles][M][TP] outgoing messages P_k p~_k
@@ -63,7 +64,8 @@ struct EvalArgs {
     double* partial;                   // [n_tiles][B] tile gradient sums
     double* logl_part;                 // [n_pb] sum_s w_s log L_s of each pattern block
     int* flag_part;                    // [n_pb] 1 NaN, 2 zero likelihood in the block
-    double* partial2;                  // [n_pb][B] tile Hessian sums
+    double* partial2;                  // [n_tiles][B] tile sums of the Hessian's additive part
+    double* r1;                        // [B][K][S_pad] per-site gradient parts (Hessian)
     double* grad_out;                  // [B] gradient destination
     double* hess_out;                  // [B] Hessian-diagonal destination
     double* logL_out;                  // [1] logL destination
@@ -80,7 +82,8 @@ inline size_t top_lds_bytes(const EvalArgs& a, size_t elem) { return elem * (siz
 hipError_t launch_pmat(const EvalArgs& a, int precision, hipStream_t s);
 hipError_t launch_post(const EvalArgs& a, int precision, hipStream_t s);
 hipError_t launch_logl(const EvalArgs& a, hipStream_t s);
-hipError_t launch_pre(const EvalArgs& a, int precision, hipStream_t s);
+hipError_t launch_pre(const EvalArgs& a, int precision, hipStream_t s, bool hess);
+hipError_t launch_hsum(const EvalArgs& a, hipStream_t s);
 hipError_t launch_gsum(const EvalArgs& a, hipStream_t s);
 
 

@@ -320,3 +320,11 @@ def test_fig1_three_taxon_worked_example():
     p, lsp, q, lsq = O.linear_partials(parent, t, Q, pi, [1.0], [1.0], masks, [1.0])
     q4_oracle = q[3][0, 0] * np.exp(lsq[3][0])
     assert np.abs(q4_oracle - q4).max() < 1e-15
+
+
+def test_linear_hessian_magnitude_bounds_the_hessian():
+    w = small(n_tips=9, n_cats=3, n_patterns=20, seed=44)
+    lin = O.linear_gradient(*args_of(w))
+    nh = O.naive_hessian_diag(*args_of(w))
+    assert (np.abs(lin["hess"]) <= lin["abs_hess"] * (1 + 1e-12)).all()
+    assert np.allclose(lin["abs_hess"], nh["abs_hess"], rtol=1e-11, atol=0)

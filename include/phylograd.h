@@ -142,6 +142,14 @@ int pg_hessian_diag(pg_ctx* ctx, double* grad, double* hess);
 int pg_logL_and_grad_device(pg_ctx* ctx, const double* d_t, double* d_logL,
                             double* d_grad);
 
+/* Device-pointer pre-order pass: the gradient of the partials left by the
+ * last evaluation (pg_logL_and_grad_device with d_grad == NULL, pg_logL,
+ * ...) is written to d_grad[2N-2] (device) asynchronously on the context's
+ * stream; no host synchronisation.  This is the backward of an autograd
+ * function whose forward was the logL-only evaluation.  PG_E_STATE if there
+ * are no resident partials. */
+int pg_grad_device(pg_ctx* ctx, double* d_grad);
+
 /* Device-side status of the last device-pointer evaluation (waits for the
  * stream): PG_OK, PG_E_INVALID (bad t) or PG_E_ZERO_LIK. */
 int pg_status(pg_ctx* ctx);

@@ -58,6 +58,7 @@ _SIGNATURES = [
     ("pg_grad", ctypes.c_int, [_vp, _vp]),
     ("pg_hessian_diag", ctypes.c_int, [_vp, _vp, _vp]),
     ("pg_logL_and_grad_device", ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    ("pg_grad_device", ctypes.c_int, [_vp, _vp]),
     ("pg_status", ctypes.c_int, [_vp]),
     ("pg_set_timing", ctypes.c_int, [_vp, ctypes.c_int]),
     ("pg_get_timing", ctypes.c_int, [_vp, _vp, _vp]),
@@ -193,6 +194,11 @@ def pg_logL_and_grad_device(ctx, d_t, d_logL, d_grad):
                                                ctypes.c_void_p(d_grad) if d_grad else None))
 
 
+def pg_grad_device(ctx, d_grad):
+    """Device address (int); asynchronous on the context's stream."""
+    _check(ctx, load().pg_grad_device(ctx, ctypes.c_void_p(d_grad)))
+
+
 def pg_status(ctx):
     return load().pg_status(ctx)
 
@@ -274,6 +280,9 @@ class Context:
 
     def logL_and_grad_device(self, d_t, d_logL, d_grad):
         pg_logL_and_grad_device(self.handle, d_t, d_logL, d_grad)
+
+    def grad_device(self, d_grad):
+        pg_grad_device(self.handle, d_grad)
 
     def status(self):
         return pg_status(self.handle)

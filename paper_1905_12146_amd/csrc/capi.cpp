@@ -738,6 +738,21 @@ int pg_logL_and_grad_device(pg_ctx* c, const double* d_t, double* d_logL, double
     });
 }
 
+int pg_grad_device(pg_ctx* c, double* d_grad) {
+    if (!c) return PG_E_INVALID;
+    if (!d_grad) return fail(c, PG_E_INVALID, "NULL d_grad");
+    if (!c->have_partials || c->dev_stale)
+        return fail(c, PG_E_STATE, "no resident partials: evaluate logL first");
+    return guarded(c, [&] {
+        PG_HIP(c, hipSetDevice(c->device));
+        EvalArgs a = c->args;
+        a.grad_out = d_grad;
+        // the logL reduction of the backward pass goes to the context's own
+        // buffer, not to the caller's forward output
+        return enqueue_backward(c, a);
+    });
+}
+
 int pg_status(pg_ctx* c) {
     if (!c) return PG_E_INVALID;
     if (!c->device_pending) return PG_OK;

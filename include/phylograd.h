@@ -169,6 +169,63 @@ int64_t pg_device_bytes(const pg_ctx* ctx);
 int64_t pg_footprint_bytes(int32_t n_tips, int32_t n_patterns, int32_t n_states,
                            int32_t n_cats, int precision);
 
+/* ---- serving: many gradient sessions with continuous batching --------
+ *
+ * A server owns a worker thread and an HBM budget.  pg_server_open creates a
+ * session (its own tree, patterns and model, checked as by pg_set_*), which
+ * waits in arrival order until its device footprint (pg_footprint_bytes)
+ * fits next to the admitted sessions and fewer than max_sessions are
+ * admitted.  pg_server_submit queues one evaluation (logL and, if
+ * want_grad, the gradient) with host branch lengths t[2N-2]; the worker runs
+ * the oldest queued call of every admitted session together as one batch
+ * (one launch per kernel for all of them), and calls that arrive meanwhile
+ * join the next batch.  A call gives the same result, bit for bit, whether
+ * it runs alone or in a batch.  pg_server_wait blocks until a call is done,
+ * copies logL and grad (caller-allocated, 2N-2), and reports the time from
+ * submit to completion.  pg_server_close lets the session's queued calls
+ * finish, then frees its device memory, which admits waiting sessions.
+ * Server functions are thread-safe. */
+typedef struct pg_server pg_server;
+
+/* Errors: PG_E_INVALID (NULL, budget <= 0, max_sessions < 1), PG_E_DEVICE. */
+int pg_server_create(int device, int precision, int64_t hbm_budget_bytes, int32_t max_sessions,
+                     pg_server** out);
+/* Stops the worker (queued calls of admitted sessions finish first) and
+ * frees everything. */
+void pg_server_destroy(pg_server* srv);
+const char* pg_server_last_error(const pg_server* srv);
+
+/* Arguments as pg_set_tree, pg_set_patterns and pg_set_model.  Errors: those
+ * of the pg_set_* calls, PG_E_OOM if the session alone exceeds the budget. */
+int pg_server_open(pg_server* srv, int32_t n_tips, const int32_t* parent, int32_t n_patterns,
+                   int32_t n_states, const uint64_t* tip_masks, const double* weights,
+                   const double* Q, const double* root_freqs, int32_t n_cats,
+                   const double* cat_rates, const double* cat_weights, int64_t* session);
+
+/* t is copied.  Errors: PG_E_STATE (unknown or closing session),
+ * PG_E_INVALID (t not finite or < 0). */
+int pg_server_submit(pg_server* srv, int64_t session, const double* t, int32_t want_grad,
+                     int64_t* ticket);
+
+/* Returns the call's status (PG_OK, PG_E_ZERO_LIK, PG_E_DEVICE, ...); logL,
+ * grad and latency_ns may be NULL.  A ticket can be waited for once. */
+int pg_server_wait(pg_server* srv, int64_t ticket, double* logL, double* grad, int64_t* latency_ns);
+
+int pg_server_close(pg_server* srv, int64_t session);
+
+/* Counters, written to out[0..min(n, PG_SRV_STAT_COUNT)-1]: */
+#define PG_SRV_STEPS          0  /* batches run                          */
+#define PG_SRV_CALLS          1  /* calls completed                      */
+#define PG_SRV_MAX_BATCH      2  /* largest batch                        */
+#define PG_SRV_ADMITTED_TOTAL 3  /* sessions ever admitted               */
+#define PG_SRV_ADMITTED_NOW   4  /* sessions admitted now                */
+#define PG_SRV_WAITING_NOW    5  /* sessions waiting for admission now   */
+#define PG_SRV_IN_USE_BYTES   6  /* device bytes of admitted sessions    */
+#define PG_SRV_PEAK_BYTES     7  /* largest in-use bytes so far          */
+#define PG_SRV_MAX_WAITING    8  /* longest admission queue so far       */
+#define PG_SRV_STAT_COUNT     9
+int pg_server_stats(pg_server* srv, int64_t* out, int32_t n);
+
 #ifdef __cplusplus
 }
 #endif

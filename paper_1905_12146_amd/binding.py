@@ -64,6 +64,15 @@ _SIGNATURES = [
     ("pg_get_timing", ctypes.c_int, [_vp, _vp, _vp]),
     ("pg_device_bytes", _i64, [_vp]),
     ("pg_footprint_bytes", _i64, [_i32, _i32, _i32, _i32, ctypes.c_int]),
+    ("pg_server_create", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64, _i32, ctypes.POINTER(_vp)]),
+    ("pg_server_destroy", None, [_vp]),
+    ("pg_server_last_error", ctypes.c_char_p, [_vp]),
+    ("pg_server_open", ctypes.c_int, [_vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp,
+                                      ctypes.POINTER(_i64)]),
+    ("pg_server_submit", ctypes.c_int, [_vp, _i64, _vp, _i32, ctypes.POINTER(_i64)]),
+    ("pg_server_wait", ctypes.c_int, [_vp, _i64, _vp, _vp, ctypes.POINTER(_i64)]),
+    ("pg_server_close", ctypes.c_int, [_vp, _i64]),
+    ("pg_server_stats", ctypes.c_int, [_vp, _vp, _i32]),
 ]
 EXPORTED = [name for name, _, _ in _SIGNATURES]
 
@@ -220,6 +229,76 @@ def pg_device_bytes(ctx):
 
 def pg_footprint_bytes(n_tips, n_patterns, n_states, n_cats, precision=PG_FP64):
     return int(load().pg_footprint_bytes(n_tips, n_patterns, n_states, n_cats, precision))
+
+
+# -- serving -------------------------------------------------------------------
+
+SRV_STAT_NAMES = ("steps", "calls", "max_batch", "admitted_total", "admitted_now", "waiting_now",
+                  "in_use_bytes", "peak_bytes", "max_waiting")
+
+
+def _check_srv(srv, code):
+    if code != PG_OK:
+        raise PhyloGradError(code, load().pg_server_last_error(srv).decode(errors="replace"))
+
+
+def pg_server_create(device=0, precision=PG_FP32, hbm_budget_bytes=32 << 30, max_sessions=64):
+    h = ctypes.c_void_p()
+    code = load().pg_server_create(int(device), int(precision), int(hbm_budget_bytes), int(max_sessions),
+                                   ctypes.byref(h))
+    if code != PG_OK:
+        raise PhyloGradError(code, load().pg_last_error(None).decode(errors="replace") or "pg_server_create")
+    return h
+
+
+def pg_server_destroy(srv):
+    load().pg_server_destroy(srv)
+
+
+def pg_server_last_error(srv):
+    return load().pg_server_last_error(srv).decode(errors="replace")
+
+
+def pg_server_open(srv, parent, tip_masks, weights, Q, pi, rates, cat_weights):
+    parent = np.ascontiguousarray(parent, dtype=np.int32)
+    tip_masks = np.ascontiguousarray(tip_masks, dtype=np.uint64)
+    weights = np.ascontiguousarray(weights, dtype=np.float64)
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    pi = np.ascontiguousarray(pi, dtype=np.float64)
+    rates = np.ascontiguousarray(rates, dtype=np.float64)
+    cat_weights = np.ascontiguousarray(cat_weights, dtype=np.float64)
+    sid = ctypes.c_int64()
+    _check_srv(srv, load().pg_server_open(srv, (len(parent) + 1) // 2, _ptr(parent), tip_masks.shape[1],
+                                          Q.shape[0], _ptr(tip_masks), _ptr(weights), _ptr(Q), _ptr(pi),
+                                          len(rates), _ptr(rates), _ptr(cat_weights), ctypes.byref(sid)))
+    return sid.value
+
+
+def pg_server_submit(srv, session, t, want_grad=True):
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    tk = ctypes.c_int64()
+    _check_srv(srv, load().pg_server_submit(srv, int(session), _ptr(t), 1 if want_grad else 0,
+                                            ctypes.byref(tk)))
+    return tk.value
+
+
+def pg_server_wait(srv, ticket, n_branches):
+    """Returns (status, logL, grad, latency_ns); status is a PG_* code."""
+    logL = np.zeros(1)
+    grad = np.zeros(n_branches)
+    lat = ctypes.c_int64()
+    code = load().pg_server_wait(srv, int(ticket), _ptr(logL), _ptr(grad), ctypes.byref(lat))
+    return code, float(logL[0]), grad, lat.value
+
+
+def pg_server_close(srv, session):
+    _check_srv(srv, load().pg_server_close(srv, int(session)))
+
+
+def pg_server_stats(srv):
+    out = np.zeros(len(SRV_STAT_NAMES), dtype=np.int64)
+    _check_srv(srv, load().pg_server_stats(srv, _ptr(out), len(out)))
+    return dict(zip(SRV_STAT_NAMES, out.tolist()))
 
 
 class Context:

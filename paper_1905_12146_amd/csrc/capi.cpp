@@ -427,6 +427,23 @@ int guarded(pg_ctx* c, F&& body) {
 
 }  // namespace
 
+namespace pg {
+
+// Device state of a context for the serving scheduler: allocate and upload
+// if needed (blocking), then hand out its EvalArgs.
+int ctx_prepare(pg_ctx* c) {
+    return guarded(c, [&] {
+        int r = upload(c);
+        if (r == PG_OK) c->have_partials = false;
+        return r;
+    });
+}
+EvalArgs ctx_args(const pg_ctx* c) { return c->args; }
+int ctx_precision(const pg_ctx* c) { return c->precision; }
+const char* ctx_error(const pg_ctx* c) { return c->err.c_str(); }
+
+}  // namespace pg
+
 extern "C" {
 
 int pg_create(int device, int precision, pg_ctx** out) {

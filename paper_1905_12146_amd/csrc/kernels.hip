@@ -303,8 +303,8 @@ __device__ inline void matmul_reg(const double A[M][M], const double B[M][M], do
 
 // One thread per (branch, category); whole matrices in registers (small M).
 template <int M, typename T>
-__global__ void __launch_bounds__(256) pmat_reg_kernel(EvalArgs a) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void pmat_reg_body(const EvalArgs& a, int block) {
+    const int idx = block * 256 + threadIdx.x;
     if (idx >= a.n_branches * a.K) return;
     const int b = idx / a.K, l = idx % a.K;
     const double tb = a.t[b];
@@ -351,9 +351,9 @@ __global__ void __launch_bounds__(256) pmat_reg_kernel(EvalArgs a) {
 
 // One workgroup per (branch, category); matrices in LDS (larger M).
 template <int M, typename T>
-__global__ void __launch_bounds__(256) pmat_lds_kernel(EvalArgs a) {
+__device__ inline void pmat_lds_body(const EvalArgs& a, int block) {
     __shared__ double A[M * M], G[M * M], W[M * M];
-    const int idx = blockIdx.x;
+    const int idx = block;
     const int b = idx / a.K, l = idx % a.K;
     const double tb = a.t[b];
     T* out = static_cast<T*>(a.P) + ((size_t)b * a.K + l) * M * M;
@@ -461,11 +461,8 @@ __device__ inline void post_node(const EvalArgs& a, int4 nd, int l, int tile, in
 }
 
 template <int M, typename T>
-__global__ void __launch_bounds__(node_slots(M) * TP) __attribute__((amdgpu_waves_per_eu(RowMat<M>::value ? 4 : 1)))
-post_kernel(EvalArgs a) {
+__device__ inline void post_body(const EvalArgs& a, int tile, int4* lds_sched) {
     constexpr int NS = node_slots(M);
-    extern __shared__ int4 lds_sched[];
-    const int tile = blockIdx.x;
     const int l = tile / a.n_pb, pb = tile % a.n_pb;
     const int ps = threadIdx.x % TP, ns = threadIdx.x / TP;
     const int s = pb * TP + ps;
@@ -764,11 +761,8 @@ __host__ __device__ constexpr int pre_waves(int M) {
 }
 
 template <int M, typename T, bool HESS>
-__global__ void __launch_bounds__(pre_slots<T>(M) * TP) __attribute__((amdgpu_waves_per_eu(pre_waves<T>(M))))
-pre_kernel(EvalArgs a) {
+__device__ inline void pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
     constexpr int NS = pre_slots<T>(M);
-    extern __shared__ int4 lds_sched[];
-    const int tile = blockIdx.x;
     const int l = tile / a.n_pb, pb = tile % a.n_pb;
     const int ps = threadIdx.x % TP, ns = threadIdx.x / TP;
     const int s = pb * TP + ps;
@@ -869,15 +863,15 @@ pre_kernel(EvalArgs a) {
 constexpr int GS_THREADS = 1024;
 constexpr int GS_SUB = GS_THREADS / GS_BRANCHES;
 
-__global__ void __launch_bounds__(GS_THREADS) gsum_kernel(EvalArgs a) {
+__device__ inline void gsum_body(const EvalArgs& a, int block) {
     const int nbc = gsum_blocks(a.n_branches);
-    if ((int)blockIdx.x == nbc) {
+    if (block == nbc) {
         finish_logl<GS_THREADS>(a);
         return;
     }
     const int B = a.n_branches;
     const int bl = threadIdx.x % GS_BRANCHES, sl = threadIdx.x / GS_BRANCHES;
-    const int b = blockIdx.x * GS_BRANCHES + bl;
+    const int b = block * GS_BRANCHES + bl;
     // tile sums t = sl, sl + GS_SUB, ... added in increasing t; a chunk of
     // GS_UNROLL loads is issued before any of it is added (out-of-range
     // entries are +0.0, which leaves the sum unchanged)
@@ -904,6 +898,63 @@ __global__ void __launch_bounds__(GS_THREADS) gsum_kernel(EvalArgs a) {
         __syncthreads();
     }
     if (sl == 0 && b < B) a.grad_out[b] = red[0][bl];
+}
+
+// ---------------------------------------------------------------- entry points
+//
+// Each kernel has a single-evaluation entry (EvalArgs by value, block =
+// blockIdx.x) and a batched entry for continuous batching: reqs[] holds the
+// EvalArgs of every evaluation in the batch and map[blockIdx.x] = {request,
+// block within that request}, so one launch covers all of them while each
+// request keeps exactly the blocks, order and results it has alone.
+
+template <int M, typename T>
+__global__ void __launch_bounds__(256) pmat_reg_kernel(EvalArgs a) { pmat_reg_body<M, T>(a, blockIdx.x); }
+template <int M, typename T>
+__global__ void __launch_bounds__(256) pmat_reg_batch(const EvalArgs* __restrict__ reqs, const int2* __restrict__ map) {
+    const int2 m = map[blockIdx.x];
+    pmat_reg_body<M, T>(reqs[m.x], m.y);
+}
+template <int M, typename T>
+__global__ void __launch_bounds__(256) pmat_lds_kernel(EvalArgs a) { pmat_lds_body<M, T>(a, blockIdx.x); }
+template <int M, typename T>
+__global__ void __launch_bounds__(256) pmat_lds_batch(const EvalArgs* __restrict__ reqs, const int2* __restrict__ map) {
+    const int2 m = map[blockIdx.x];
+    pmat_lds_body<M, T>(reqs[m.x], m.y);
+}
+
+template <int M, typename T>
+__global__ void __launch_bounds__(node_slots(M) * TP) __attribute__((amdgpu_waves_per_eu(RowMat<M>::value ? 4 : 1)))
+post_kernel(EvalArgs a) {
+    extern __shared__ int4 lds_dyn[];
+    post_body<M, T>(a, blockIdx.x, lds_dyn);
+}
+template <int M, typename T>
+__global__ void __launch_bounds__(node_slots(M) * TP) __attribute__((amdgpu_waves_per_eu(RowMat<M>::value ? 4 : 1)))
+post_batch(const EvalArgs* __restrict__ reqs, const int2* __restrict__ map) {
+    extern __shared__ int4 lds_dyn[];
+    const int2 m = map[blockIdx.x];
+    post_body<M, T>(reqs[m.x], m.y, lds_dyn);
+}
+
+template <int M, typename T, bool HESS>
+__global__ void __launch_bounds__(pre_slots<T>(M) * TP) __attribute__((amdgpu_waves_per_eu(pre_waves<T>(M))))
+pre_kernel(EvalArgs a) {
+    extern __shared__ int4 lds_dyn[];
+    pre_body<M, T, HESS>(a, blockIdx.x, lds_dyn);
+}
+template <int M, typename T>
+__global__ void __launch_bounds__(pre_slots<T>(M) * TP) __attribute__((amdgpu_waves_per_eu(pre_waves<T>(M))))
+pre_batch(const EvalArgs* __restrict__ reqs, const int2* __restrict__ map) {
+    extern __shared__ int4 lds_dyn[];
+    const int2 m = map[blockIdx.x];
+    pre_body<M, T, false>(reqs[m.x], m.y, lds_dyn);
+}
+
+__global__ void __launch_bounds__(GS_THREADS) gsum_kernel(EvalArgs a) { gsum_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(GS_THREADS) gsum_batch(const EvalArgs* __restrict__ reqs, const int2* __restrict__ map) {
+    const int2 m = map[blockIdx.x];
+    gsum_body(reqs[m.x], m.y);
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -1002,6 +1053,40 @@ hipError_t launch_hsum(const EvalArgs& a, hipStream_t st) {
 hipError_t launch_gsum(const EvalArgs& a, hipStream_t st) {
     gsum_kernel<<<gsum_blocks(a.n_branches) + 1, GS_THREADS, 0, st>>>(a);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- batched launches
+
+int pmat_blocks(const EvalArgs& a) {
+    return a.M <= 8 ? (a.n_branches * a.K + 255) / 256 : a.n_branches * a.K;
+}
+int traversal_blocks(const EvalArgs& a) { return a.n_tiles; }
+int gsum_total_blocks(const EvalArgs& a) { return gsum_blocks(a.n_branches) + 1; }
+
+size_t post_lds_bytes(const EvalArgs& a) { return sched_lds_bytes(a); }
+size_t pre_lds_bytes(const EvalArgs& a, int precision) {
+    return sched_lds_bytes(a) + top_lds_bytes(a, precision == PG_FP32 ? 4 : 8);
+}
+
+template <int M, typename T>
+static hipError_t batch_launch(const BatchLaunch& b, hipStream_t st) {
+    if (b.pmat_blocks > 0) {
+        if constexpr (M <= 8) pmat_reg_batch<M, T><<<b.pmat_blocks, 256, 0, st>>>(b.reqs, b.pmat_map);
+        else pmat_lds_batch<M, T><<<b.pmat_blocks, 256, 0, st>>>(b.reqs, b.pmat_map);
+    }
+    post_batch<M, T><<<b.trav_blocks, node_slots(M) * TP, b.post_lds, st>>>(b.reqs, b.trav_map);
+    pre_batch<M, T><<<b.trav_blocks, pre_slots<T>(M) * TP, b.pre_lds, st>>>(b.reqs, b.trav_map);
+    gsum_batch<<<b.gsum_blocks, GS_THREADS, 0, st>>>(b.reqs, b.gsum_map);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchLaunch& b, hipStream_t st) {
+    const int M = b.M, precision = b.precision;
+    if (M == 4 && precision == PG_FP64) return batch_launch<4, double>(b, st);
+    if (M == 4 && precision == PG_FP32) return batch_launch<4, float>(b, st);
+    if (M == 20 && precision == PG_FP64) return batch_launch<20, double>(b, st);
+    if (M == 20 && precision == PG_FP32) return batch_launch<20, float>(b, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace pg

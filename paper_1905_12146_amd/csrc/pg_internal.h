@@ -84,6 +84,34 @@ hipError_t launch_post(const EvalArgs& a, int precision, hipStream_t s);
 hipError_t launch_logl(const EvalArgs& a, hipStream_t s);
 hipError_t launch_pre(const EvalArgs& a, int precision, hipStream_t s, bool hess);
 hipError_t launch_hsum(const EvalArgs& a, hipStream_t s);
+
+// One continuous-batching step: every request's pmat, post, pre and gsum
+// blocks in one launch each.  reqs and the maps are device arrays; map
+// entries are {request index, block within the request}.
+struct BatchLaunch {
+    int M, precision;
+    const EvalArgs* reqs;
+    const int2* pmat_map;
+    const int2* trav_map;
+    const int2* gsum_map;
+    int pmat_blocks, trav_blocks, gsum_blocks;
+    size_t post_lds, pre_lds;
+};
+int pmat_blocks(const EvalArgs& a);
+int traversal_blocks(const EvalArgs& a);
+int gsum_total_blocks(const EvalArgs& a);
+size_t post_lds_bytes(const EvalArgs& a);
+size_t pre_lds_bytes(const EvalArgs& a, int precision);
+hipError_t launch_batch(const BatchLaunch& b, hipStream_t s);
+
+// Context internals used by the serving scheduler (capi.cpp).
+}  // namespace pg
+struct pg_ctx;
+namespace pg {
+int ctx_prepare(pg_ctx* c);
+EvalArgs ctx_args(const pg_ctx* c);
+int ctx_precision(const pg_ctx* c);
+const char* ctx_error(const pg_ctx* c);
 hipError_t launch_gsum(const EvalArgs& a, hipStream_t s);
 
 

@@ -1,0 +1,469 @@
+// Serving scheduler: many independent gradient sessions on one GPU with
+// admission by HBM footprint and continuous batching.
+//
+// A session owns a context (tree, patterns, model, resident partials).  A
+// session is admitted when the device bytes it needs fit the budget next to
+// the admitted sessions and a session slot is free; otherwise it waits in
+// arrival order.  The worker thread repeatedly takes, from every admitted
+// session with a pending call, its oldest call and runs all of them as one
+// batch: one launch each of the transition-matrix, post-order, pre-order and
+// reduction kernels, whose blocks are mapped to (call, block-of-that-call).
+// A call's blocks, their order and its reductions are the same whether it
+// runs alone or in a batch, so its result is bitwise the same.  Calls that
+// arrive while a batch runs join the next one.  Closing a session releases
+// its device memory and lets waiting sessions in.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "pg_internal.h"
+
+using namespace pg;
+
+namespace {
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct Call {
+    int64_t session = 0;
+    std::vector<double> t;
+    bool want_grad = true;
+    double logL = 0.0;
+    std::vector<double> grad;
+    int status = 0;
+    int64_t t_submit = 0, t_start = 0, t_done = 0;
+    bool done = false;
+};
+
+struct Session {
+    pg_ctx* ctx = nullptr;
+    int64_t footprint = 0;
+    int n_branches = 0;
+    int M = 0;
+    bool admitted = false;
+    bool closing = false;
+    std::deque<int64_t> pending;
+};
+
+}  // namespace
+
+struct pg_server {
+    int device = 0, precision = PG_FP64;
+    int64_t budget = 0, in_use = 0, peak = 0;
+    int max_sessions = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::map<int64_t, Session> sessions;   // ordered by id = arrival order
+    std::deque<int64_t> admit_q;
+    std::map<int64_t, Call> calls;
+    int64_t next_session = 1, next_ticket = 1;
+    bool stop = false;
+    std::thread worker;
+
+    // staging: one pinned host buffer and one device buffer per direction
+    void* h_in = nullptr;
+    void* d_in = nullptr;
+    size_t in_cap = 0;
+    void* h_out = nullptr;
+    void* d_out = nullptr;
+    size_t out_cap = 0;
+
+    // statistics
+    int64_t steps = 0, calls_done = 0, batched_calls = 0, max_batch = 0, admitted_total = 0;
+    int64_t max_waiting = 0;
+};
+
+namespace {
+
+size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+int grow(pg_server* s, void** h, void** d, size_t* cap, size_t need) {
+    if (*cap >= need) return PG_OK;
+    size_t n = std::max(need, *cap * 2);
+    if (*h) (void)hipHostFree(*h);
+    if (*d) (void)hipFree(*d);
+    *h = nullptr;
+    *d = nullptr;
+    *cap = 0;
+    if (hipHostMalloc(h, n) != hipSuccess) return PG_E_OOM;
+    if (hipMalloc(d, n) != hipSuccess) return PG_E_OOM;
+    *cap = n;
+    (void)s;
+    return PG_OK;
+}
+
+// Admit waiting sessions in arrival order while they fit.  Caller holds mu.
+void admit(pg_server* s) {
+    int admitted = 0;
+    for (auto& kv : s->sessions)
+        if (kv.second.admitted) ++admitted;
+    while (!s->admit_q.empty()) {
+        auto it = s->sessions.find(s->admit_q.front());
+        if (it == s->sessions.end()) {
+            s->admit_q.pop_front();
+            continue;
+        }
+        Session& ss = it->second;
+        if (admitted >= s->max_sessions || s->in_use + ss.footprint > s->budget) break;
+        s->admit_q.pop_front();
+        const int r = ctx_prepare(ss.ctx);
+        if (r != PG_OK) {
+            // fail every pending call of this session
+            for (int64_t tk : ss.pending) {
+                Call& c = s->calls[tk];
+                c.status = r;
+                c.done = true;
+                c.t_done = now_ns();
+            }
+            ss.pending.clear();
+            ss.closing = true;
+            continue;
+        }
+        ss.admitted = true;
+        s->in_use += ss.footprint;
+        s->peak = std::max(s->peak, s->in_use);
+        ++admitted;
+        ++s->admitted_total;
+    }
+    s->max_waiting = std::max<int64_t>(s->max_waiting, (int64_t)s->admit_q.size());
+}
+
+// Free sessions that asked to close and have no pending calls.  Caller holds mu.
+void reap(pg_server* s) {
+    for (auto it = s->sessions.begin(); it != s->sessions.end();) {
+        Session& ss = it->second;
+        if (ss.closing && ss.pending.empty()) {
+            if (ss.admitted) s->in_use -= ss.footprint;
+            pg_destroy(ss.ctx);
+            it = s->sessions.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+struct Item {
+    int64_t ticket;
+    Session* sess;
+    Call* call;
+    EvalArgs args;
+};
+
+// Run one batch of calls with the same state count; mu is not held.
+int run_group(pg_server* s, std::vector<Item>& items) {
+    const int n = (int)items.size();
+    // input layout: [t of every call][EvalArgs x n][pmat map][trav map][gsum map]
+    size_t t_total = 0;
+    int pm = 0, tr = 0, gs = 0;
+    size_t post_lds = 0, pre_lds = 0;
+    for (auto& it : items) {
+        t_total += it.args.n_branches;
+        pm += pmat_blocks(it.args);
+        tr += traversal_blocks(it.args);
+        gs += gsum_total_blocks(it.args);
+        post_lds = std::max(post_lds, post_lds_bytes(it.args));
+        pre_lds = std::max(pre_lds, pre_lds_bytes(it.args, s->precision));
+    }
+    const size_t off_t = 0;
+    const size_t off_args = align16(off_t + sizeof(double) * t_total);
+    const size_t off_pm = align16(off_args + sizeof(EvalArgs) * n);
+    const size_t off_tr = align16(off_pm + sizeof(int2) * pm);
+    const size_t off_gs = align16(off_tr + sizeof(int2) * tr);
+    const size_t in_bytes = align16(off_gs + sizeof(int2) * gs);
+    // output layout: [logL x n][status x n][grad of every call]
+    const size_t o_logl = 0;
+    const size_t o_status = align16(sizeof(double) * n);
+    const size_t o_grad = align16(o_status + sizeof(int) * n);
+    const size_t out_bytes = align16(o_grad + sizeof(double) * t_total);
+    int r;
+    if ((r = grow(s, &s->h_in, &s->d_in, &s->in_cap, in_bytes))) return r;
+    if ((r = grow(s, &s->h_out, &s->d_out, &s->out_cap, out_bytes))) return r;
+    char* hi = static_cast<char*>(s->h_in);
+    char* di = static_cast<char*>(s->d_in);
+    char* dout = static_cast<char*>(s->d_out);
+    double* ht = reinterpret_cast<double*>(hi + off_t);
+    EvalArgs* ha = reinterpret_cast<EvalArgs*>(hi + off_args);
+    int2* hpm = reinterpret_cast<int2*>(hi + off_pm);
+    int2* htr = reinterpret_cast<int2*>(hi + off_tr);
+    int2* hgs = reinterpret_cast<int2*>(hi + off_gs);
+    size_t toff = 0;
+    int ipm = 0, itr = 0, igs = 0;
+    for (int q = 0; q < n; ++q) {
+        Item& it = items[q];
+        EvalArgs a = it.args;
+        std::memcpy(ht + toff, it.call->t.data(), sizeof(double) * a.n_branches);
+        a.t = reinterpret_cast<const double*>(di + off_t) + toff;
+        a.logL_out = reinterpret_cast<double*>(dout + o_logl) + q;
+        a.status = reinterpret_cast<int*>(dout + o_status) + q;
+        a.grad_out = reinterpret_cast<double*>(dout + o_grad) + toff;
+        ha[q] = a;
+        for (int b = 0, nb = pmat_blocks(a); b < nb; ++b) hpm[ipm++] = make_int2(q, b);
+        for (int b = 0, nb = traversal_blocks(a); b < nb; ++b) htr[itr++] = make_int2(q, b);
+        for (int b = 0, nb = gsum_total_blocks(a); b < nb; ++b) hgs[igs++] = make_int2(q, b);
+        toff += a.n_branches;
+    }
+    hipError_t e;
+    if ((e = hipMemcpyAsync(s->d_in, s->h_in, in_bytes, hipMemcpyHostToDevice, s->stream)) != hipSuccess)
+        return PG_E_DEVICE;
+    BatchLaunch bl{};
+    bl.M = items[0].args.M;
+    bl.precision = s->precision;
+    bl.reqs = reinterpret_cast<const EvalArgs*>(di + off_args);
+    bl.pmat_map = reinterpret_cast<const int2*>(di + off_pm);
+    bl.trav_map = reinterpret_cast<const int2*>(di + off_tr);
+    bl.gsum_map = reinterpret_cast<const int2*>(di + off_gs);
+    bl.pmat_blocks = pm;
+    bl.trav_blocks = tr;
+    bl.gsum_blocks = gs;
+    bl.post_lds = post_lds;
+    bl.pre_lds = pre_lds;
+    if ((e = launch_batch(bl, s->stream)) != hipSuccess) return PG_E_DEVICE;
+    if ((e = hipMemcpyAsync(s->h_out, s->d_out, out_bytes, hipMemcpyDeviceToHost, s->stream)) != hipSuccess)
+        return PG_E_DEVICE;
+    if ((e = hipStreamSynchronize(s->stream)) != hipSuccess) return PG_E_DEVICE;
+    const char* ho = static_cast<const char*>(s->h_out);
+    toff = 0;
+    for (int q = 0; q < n; ++q) {
+        Call* c = items[q].call;
+        c->logL = reinterpret_cast<const double*>(ho + o_logl)[q];
+        const int st = reinterpret_cast<const int*>(ho + o_status)[q];
+        c->status = st == 1 ? PG_E_INVALID : st == 2 ? PG_E_ZERO_LIK : PG_OK;
+        const int B = items[q].args.n_branches;
+        if (c->want_grad) {
+            const double* g = reinterpret_cast<const double*>(ho + o_grad) + toff;
+            c->grad.assign(g, g + B);
+        }
+        toff += B;
+    }
+    return PG_OK;
+}
+
+void worker_loop(pg_server* s) {
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        reap(s);
+        admit(s);
+        std::vector<Item> batch;
+        for (auto& kv : s->sessions) {
+            Session& ss = kv.second;
+            if (!ss.admitted || ss.pending.empty()) continue;
+            const int64_t tk = ss.pending.front();
+            Call& c = s->calls[tk];
+            batch.push_back(Item{tk, &ss, &c, ctx_args(ss.ctx)});
+        }
+        if (batch.empty()) {
+            if (s->stop) break;
+            s->cv_work.wait(lk);
+            continue;
+        }
+        const int64_t t0 = now_ns();
+        for (auto& it : batch) it.call->t_start = t0;
+        lk.unlock();
+        // group by state count (one kernel instantiation per group)
+        std::map<int, std::vector<Item>> groups;
+        for (auto& it : batch) groups[it.args.M].push_back(it);
+        std::map<int64_t, int> result;
+        for (auto& g : groups) {
+            const int r = run_group(s, g.second);
+            for (auto& it : g.second) result[it.ticket] = r;
+        }
+        lk.lock();
+        const int64_t t1 = now_ns();
+        for (auto& it : batch) {
+            Call& c = *it.call;
+            if (result[it.ticket] != PG_OK) c.status = result[it.ticket];
+            c.t_done = t1;
+            c.done = true;
+            it.sess->pending.pop_front();
+        }
+        ++s->steps;
+        s->calls_done += (int64_t)batch.size();
+        s->batched_calls += (int64_t)batch.size();
+        s->max_batch = std::max<int64_t>(s->max_batch, (int64_t)batch.size());
+        s->cv_done.notify_all();
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int pg_server_create(int device, int precision, int64_t hbm_budget, int32_t max_sessions, pg_server** out) {
+    if (!out || hbm_budget <= 0 || max_sessions < 1) return PG_E_INVALID;
+    *out = nullptr;
+    pg_ctx* probe = nullptr;
+    int r = pg_create(device, precision, &probe);
+    if (r != PG_OK) return r;
+    pg_destroy(probe);
+    pg_server* s = nullptr;
+    try {
+        s = new pg_server();
+    } catch (...) {
+        return PG_E_OOM;
+    }
+    s->device = device;
+    s->precision = precision;
+    s->budget = hbm_budget;
+    s->max_sessions = max_sessions;
+    if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&s->stream) != hipSuccess) {
+        delete s;
+        return PG_E_DEVICE;
+    }
+    try {
+        s->worker = std::thread(worker_loop, s);
+    } catch (...) {
+        (void)hipStreamDestroy(s->stream);
+        delete s;
+        return PG_E_DEVICE;
+    }
+    *out = s;
+    return PG_OK;
+}
+
+void pg_server_destroy(pg_server* s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        for (auto& kv : s->sessions) kv.second.closing = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto& kv : s->sessions) pg_destroy(kv.second.ctx);
+        s->sessions.clear();
+    }
+    (void)hipSetDevice(s->device);
+    if (s->h_in) (void)hipHostFree(s->h_in);
+    if (s->h_out) (void)hipHostFree(s->h_out);
+    if (s->d_in) (void)hipFree(s->d_in);
+    if (s->d_out) (void)hipFree(s->d_out);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+const char* pg_server_last_error(const pg_server* s) { return s ? s->err.c_str() : ""; }
+
+int pg_server_open(pg_server* s, int32_t n_tips, const int32_t* parent, int32_t n_patterns, int32_t n_states,
+                   const uint64_t* tip_masks, const double* weights, const double* Q, const double* root_freqs,
+                   int32_t n_cats, const double* cat_rates, const double* cat_weights, int64_t* session) {
+    if (!s || !session) return PG_E_INVALID;
+    pg_ctx* c = nullptr;
+    int r = pg_create(s->device, s->precision, &c);
+    if (r != PG_OK) return r;
+    if ((r = pg_set_tree(c, n_tips, parent)) != PG_OK ||
+        (r = pg_set_patterns(c, n_patterns, n_states, tip_masks, weights)) != PG_OK ||
+        (r = pg_set_model(c, n_states, Q, root_freqs, n_cats, cat_rates, cat_weights)) != PG_OK) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->err = pg_last_error(c);
+        pg_destroy(c);
+        return r;
+    }
+    const int64_t fp = pg_footprint_bytes(n_tips, n_patterns, n_states, n_cats, s->precision);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (fp > s->budget) {
+        s->err = "session needs " + std::to_string(fp) + " device bytes, more than the budget " +
+                 std::to_string(s->budget);
+        pg_destroy(c);
+        return PG_E_OOM;
+    }
+    const int64_t id = s->next_session++;
+    Session& ss = s->sessions[id];
+    ss.ctx = c;
+    ss.footprint = fp;
+    ss.n_branches = 2 * n_tips - 2;
+    ss.M = n_states;
+    s->admit_q.push_back(id);
+    *session = id;
+    s->cv_work.notify_all();
+    return PG_OK;
+}
+
+int pg_server_submit(pg_server* s, int64_t session, const double* t, int32_t want_grad, int64_t* ticket) {
+    if (!s || !t || !ticket) return PG_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->sessions.find(session);
+    if (it == s->sessions.end() || it->second.closing) {
+        s->err = "unknown or closing session";
+        return PG_E_STATE;
+    }
+    Session& ss = it->second;
+    for (int b = 0; b < ss.n_branches; ++b)
+        if (!(t[b] >= 0.0) || t[b] == INFINITY) {
+            s->err = "branch length " + std::to_string(b) + " is not finite and >= 0";
+            return PG_E_INVALID;
+        }
+    const int64_t tk = s->next_ticket++;
+    Call& c = s->calls[tk];
+    c.session = session;
+    c.t.assign(t, t + ss.n_branches);
+    c.want_grad = want_grad != 0;
+    c.t_submit = now_ns();
+    ss.pending.push_back(tk);
+    *ticket = tk;
+    s->cv_work.notify_all();
+    return PG_OK;
+}
+
+int pg_server_wait(pg_server* s, int64_t ticket, double* logL, double* grad, int64_t* latency_ns) {
+    if (!s) return PG_E_INVALID;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->calls.find(ticket);
+    if (it == s->calls.end()) {
+        s->err = "unknown ticket";
+        return PG_E_STATE;
+    }
+    s->cv_done.wait(lk, [&] { return it->second.done; });
+    Call& c = it->second;
+    if (logL) *logL = c.logL;
+    if (grad && c.want_grad && !c.grad.empty()) std::memcpy(grad, c.grad.data(), sizeof(double) * c.grad.size());
+    if (latency_ns) *latency_ns = c.t_done - c.t_submit;
+    const int r = c.status;
+    s->calls.erase(it);
+    return r;
+}
+
+int pg_server_close(pg_server* s, int64_t session) {
+    if (!s) return PG_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->sessions.find(session);
+    if (it == s->sessions.end()) return PG_E_STATE;
+    it->second.closing = true;
+    auto q = std::find(s->admit_q.begin(), s->admit_q.end(), session);
+    if (q != s->admit_q.end() && it->second.pending.empty()) s->admit_q.erase(q);
+    s->cv_work.notify_all();
+    return PG_OK;
+}
+
+int pg_server_stats(pg_server* s, int64_t* out, int32_t n) {
+    if (!s || !out) return PG_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    int64_t admitted = 0;
+    for (auto& kv : s->sessions)
+        if (kv.second.admitted) ++admitted;
+    const int64_t v[PG_SRV_STAT_COUNT] = {s->steps,     s->calls_done, s->max_batch, s->admitted_total,
+                                          admitted,     (int64_t)s->admit_q.size(), s->in_use, s->peak,
+                                          s->max_waiting};
+    for (int i = 0; i < n && i < PG_SRV_STAT_COUNT; ++i) out[i] = v[i];
+    return PG_OK;
+}
+
+}  // extern "C"

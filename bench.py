@@ -121,6 +121,58 @@ def traffic_record(kernel, precision):
     return None if entry is None else entry["read_bytes"] + entry["write_bytes"]
 
 
+def serving_bench(args):
+    """Serve a stream of requests (N ~ U{100..2000}, S ~ U{500..5000}, 4-state,
+    K = 4, FP32 partials, `calls` dependent gradient calls each) with
+    continuous batching and with one request at a time, at arrival rates that
+    are multiples of the one-at-a-time capacity.  Prints one JSON line."""
+    from paper_1905_12146_amd import binding as B
+    from paper_1905_12146_amd.serving import Server, generate_requests, run_stream
+    from synth import serving_requests
+
+    specs = serving_requests(args.requests, qps=1.0)
+    t0 = time.perf_counter()
+    workloads = generate_requests(specs, processes=min(16, os.cpu_count() or 1))
+    gen_s = time.perf_counter() - t0
+    budget = int(args.budget_gb * (1 << 30))
+
+    def with_rate(qps):
+        gaps = [s.arrival_s for s in specs]
+        return [type(s)(rid=s.rid, arrival_s=g / qps, n_tips=s.n_tips, n_patterns=s.n_patterns, seed=s.seed)
+                for s, g in zip(specs, gaps)]
+
+    # warm-up (kernel loading, allocator) on a few requests
+    with Server(0, B.PG_FP32, budget, args.max_sessions) as srv:
+        run_stream(srv, with_rate(1e9)[:4], workloads[:4], calls=2)
+    # one-at-a-time capacity: all requests queued at t = 0, one admitted at a time
+    with Server(0, B.PG_FP32, budget, 1) as srv:
+        cap = run_stream(srv, with_rate(1e9), workloads, calls=args.calls)
+    capacity = cap["completed"] / cap["wall_s"]
+    runs = []
+    for f in [float(x) for x in args.qps_factors.split(",") if x]:
+        qps = f * capacity
+        row = {"qps_factor": f, "qps": round(qps, 2)}
+        for mode, slots in (("batched", args.max_sessions), ("one_at_a_time", 1)):
+            with Server(0, B.PG_FP32, budget, slots) as srv:
+                r = run_stream(srv, with_rate(qps), workloads, calls=args.calls)
+                st = srv.stats()
+            r.pop("results")
+            row[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items() if k != "errors"}
+            row[mode]["errors"] = len(r["errors"])
+            row[mode]["max_batch"] = st["max_batch"]
+            row[mode]["peak_gb"] = round(st["peak_bytes"] / 2 ** 30, 2)
+            row[mode]["max_waiting"] = st["max_waiting"]
+        runs.append(row)
+    out = {"metric": "served gradient calls: p50/p99 request latency and throughput",
+           "workload": f"{args.requests} requests, N~U{{100..2000}}, S~U{{500..5000}}, 4-state, K=4, FP32, "
+                       f"{args.calls} calls each, Poisson arrivals",
+           "budget_gb": args.budget_gb, "max_sessions": args.max_sessions,
+           "one_at_a_time_capacity_req_per_s": round(capacity, 2),
+           "capacity_run": {"wall_s": round(cap["wall_s"], 3), "calls_per_s": round(cap["calls_per_s"], 1)},
+           "generation_s": round(gen_s, 1), "runs": runs}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,9 +184,21 @@ def main():
                     help="branches of the CPU oracle sample (0 disables the CPU leg)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (HBM counter calibration)")
+    ap.add_argument("--serving", action="store_true",
+                    help="serving benchmark: a Poisson stream of gradient sessions (continuous batching "
+                         "vs one request at a time)")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--calls", type=int, default=10)
+    ap.add_argument("--qps-factors", default="0.5,0.9,1.5",
+                    help="arrival rates as multiples of the one-at-a-time capacity")
+    ap.add_argument("--budget-gb", type=float, default=32.0)
+    ap.add_argument("--max-sessions", type=int, default=64)
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.serving:
+        serving_bench(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "

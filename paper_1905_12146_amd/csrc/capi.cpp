@@ -60,12 +60,15 @@ struct pg_ctx {
     std::map<std::string, DevBuf> bufs;
     EvalArgs args{};
 
+    // device allocator (default hipMalloc/hipFree; the serving scheduler
+    // supplies a pool so sessions reuse each other's memory)
+    DeviceAllocator* allocator = nullptr;
+
     // timing: event pairs recorded around kernels, read after the stream
     // passes them (no synchronisation between kernels)
     bool timing = false;
     double ms[PG_K_COUNT] = {0};
     int64_t launches[PG_K_COUNT] = {0};
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<hipEvent_t> ev_pool;
     struct Pending { int kid; hipEvent_t a, b; };
     std::vector<Pending> pending;
@@ -94,14 +97,23 @@ int ensure_buf(pg_ctx* c, const char* name, size_t bytes) {
     DevBuf& b = c->bufs[name];
     if (b.bytes >= bytes && b.ptr) return PG_OK;
     if (b.ptr) {
-        hipError_t e = hipFree(b.ptr);
+        if (c->allocator) {
+            c->allocator->release(b.ptr, b.bytes);
+        } else {
+            hipError_t e = hipFree(b.ptr);
+            if (e != hipSuccess) return hip_fail(c, e, "hipFree");
+        }
         b.ptr = nullptr;
         b.bytes = 0;
-        if (e != hipSuccess) return hip_fail(c, e, "hipFree");
     }
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 256));
-    if (e != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    if (c->allocator) {
+        p = c->allocator->acquire(std::max<size_t>(bytes, 256));
+        if (!p) return fail(c, PG_E_OOM, "device pool allocation failed");
+    } else {
+        hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 256));
+        if (e != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    }
     b.ptr = p;
     b.bytes = std::max<size_t>(bytes, 256);
     return PG_OK;
@@ -439,6 +451,17 @@ int ctx_prepare(pg_ctx* c) {
     });
 }
 EvalArgs ctx_args(const pg_ctx* c) { return c->args; }
+
+// A context without its own stream, events or device query, on `stream`,
+// allocating through `alloc` (serving sessions).
+pg_ctx* ctx_new_session(int device, int precision, hipStream_t stream, DeviceAllocator* alloc) {
+    pg_ctx* c = new pg_ctx();
+    c->device = device;
+    c->precision = precision;
+    c->stream = stream;
+    c->allocator = alloc;
+    return c;
+}
 int ctx_precision(const pg_ctx* c) { return c->precision; }
 const char* ctx_error(const pg_ctx* c) { return c->err.c_str(); }
 
@@ -479,8 +502,7 @@ int pg_create(int device, int precision, pg_ctx** out) {
     }
     c->device = device;
     c->precision = precision;
-    if ((e = hipSetDevice(device)) != hipSuccess || (e = hipStreamCreate(&c->own_stream)) != hipSuccess ||
-        (e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess) {
+    if ((e = hipSetDevice(device)) != hipSuccess || (e = hipStreamCreate(&c->own_stream)) != hipSuccess) {
         g_create_error = std::string("HIP setup: ") + hipGetErrorString(e);
         pg_destroy(c);
         return PG_E_DEVICE;
@@ -495,9 +517,10 @@ void pg_destroy(pg_ctx* c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto& kv : c->bufs)
-        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
-    if (c->ev0) (void)hipEventDestroy(c->ev0);
-    if (c->ev1) (void)hipEventDestroy(c->ev1);
+        if (kv.second.ptr) {
+            if (c->allocator) c->allocator->release(kv.second.ptr, kv.second.bytes);
+            else (void)hipFree(kv.second.ptr);
+        }
     for (auto& p : c->pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);

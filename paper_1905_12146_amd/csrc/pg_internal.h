@@ -104,10 +104,18 @@ size_t post_lds_bytes(const EvalArgs& a);
 size_t pre_lds_bytes(const EvalArgs& a, int precision);
 hipError_t launch_batch(const BatchLaunch& b, hipStream_t s);
 
+// Device memory source of a context (the serving scheduler's pool).
+struct DeviceAllocator {
+    virtual void* acquire(size_t bytes) = 0;
+    virtual void release(void* p, size_t bytes) = 0;
+    virtual ~DeviceAllocator() = default;
+};
+
 // Context internals used by the serving scheduler (capi.cpp).
 }  // namespace pg
 struct pg_ctx;
 namespace pg {
+pg_ctx* ctx_new_session(int device, int precision, hipStream_t stream, DeviceAllocator* alloc);
 int ctx_prepare(pg_ctx* c);
 EvalArgs ctx_args(const pg_ctx* c);
 int ctx_precision(const pg_ctx* c);

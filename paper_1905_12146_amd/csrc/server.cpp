@@ -58,6 +58,57 @@ struct Session {
     std::deque<int64_t> pending;
 };
 
+// Device memory pool: freed session buffers are kept and handed to later
+// sessions (best fit within 2x), so admission and closing avoid hipMalloc /
+// hipFree.  Cached bytes are capped; the largest blocks go first.
+class Pool : public DeviceAllocator {
+public:
+    explicit Pool(size_t cap) : cap_(cap) {}
+    ~Pool() override { trim(0); }
+    void* acquire(size_t bytes) override {
+        bytes = round(bytes);
+        auto it = free_.lower_bound(bytes);
+        if (it != free_.end() && it->first <= 2 * bytes) {
+            void* p = it->second;
+            cached_ -= it->first;
+            size_[p] = it->first;
+            free_.erase(it);
+            return p;
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            trim(0);  // give cached memory back and try once more
+            if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        }
+        size_[p] = bytes;
+        return p;
+    }
+    void release(void* p, size_t) override {
+        auto it = size_.find(p);
+        const size_t bytes = it->second;
+        size_.erase(it);
+        free_.emplace(bytes, p);
+        cached_ += bytes;
+        trim(cap_);
+    }
+    size_t cached() const { return cached_; }
+
+private:
+    static size_t round(size_t b) { return (b + 65535) & ~size_t(65535); }
+    void trim(size_t limit) {
+        while (cached_ > limit && !free_.empty()) {
+            auto it = std::prev(free_.end());
+            (void)hipFree(it->second);
+            cached_ -= it->first;
+            free_.erase(it);
+        }
+    }
+    size_t cap_;
+    size_t cached_ = 0;
+    std::multimap<size_t, void*> free_;
+    std::map<void*, size_t> size_;
+};
+
 }  // namespace
 
 struct pg_server {
@@ -66,6 +117,7 @@ struct pg_server {
     int max_sessions = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    Pool* pool = nullptr;
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -326,9 +378,11 @@ int pg_server_create(int device, int precision, int64_t hbm_budget, int32_t max_
         delete s;
         return PG_E_DEVICE;
     }
+    s->pool = new Pool((size_t)hbm_budget);
     try {
         s->worker = std::thread(worker_loop, s);
     } catch (...) {
+        delete s->pool;
         (void)hipStreamDestroy(s->stream);
         delete s;
         return PG_E_DEVICE;
@@ -356,6 +410,7 @@ void pg_server_destroy(pg_server* s) {
     if (s->h_out) (void)hipHostFree(s->h_out);
     if (s->d_in) (void)hipFree(s->d_in);
     if (s->d_out) (void)hipFree(s->d_out);
+    delete s->pool;
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -367,8 +422,12 @@ int pg_server_open(pg_server* s, int32_t n_tips, const int32_t* parent, int32_t 
                    int32_t n_cats, const double* cat_rates, const double* cat_weights, int64_t* session) {
     if (!s || !session) return PG_E_INVALID;
     pg_ctx* c = nullptr;
-    int r = pg_create(s->device, s->precision, &c);
-    if (r != PG_OK) return r;
+    try {
+        c = ctx_new_session(s->device, s->precision, s->stream, s->pool);
+    } catch (...) {
+        return PG_E_OOM;
+    }
+    int r;
     if ((r = pg_set_tree(c, n_tips, parent)) != PG_OK ||
         (r = pg_set_patterns(c, n_patterns, n_states, tip_masks, weights)) != PG_OK ||
         (r = pg_set_model(c, n_states, Q, root_freqs, n_cats, cat_rates, cat_weights)) != PG_OK) {

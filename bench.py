@@ -104,20 +104,21 @@ def calibrate_copy():
                       "GB_per_s": 2 * 2 ** 30 / (best * 1e-3) / 1e9}), flush=True)
 
 
-def traffic_record(kernel, precision):
+def traffic_record(kernel, precision, workload="C2"):
     """HBM bytes per launch measured with rocprofv3 counters for this kernel
     source (profiles/traffic.json), or None if the source has changed."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = os.path.join(ROOT, "paper_1905_12146_amd", "csrc", "kernels.hip")
+    src = os.path.join(ROOT, "paper_1905_12146_amd", "csrc",
+                       "kernels_mfma.hip" if precision == "split" else "kernels.hip")
     try:
         rec = json.load(open(path))
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("kernels_hip_sha256") != digest:
+    if rec.get("sources_sha256", {}).get(os.path.basename(src), rec.get("kernels_hip_sha256")) != digest:
         return None
-    entry = rec.get("C2", {}).get(precision, {}).get(kernel)
+    entry = rec.get(workload, {}).get(precision, {}).get(kernel)
     return None if entry is None else entry["read_bytes"] + entry["write_bytes"]
 
 
@@ -178,7 +179,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "split"], default=None,
+                    help="fp64 / fp32 (default fp64 for C2), split = split-BF16 matrix cores (C4)")
+    ap.add_argument("--workload", choices=["C2", "C4"], default="C2",
+                    help="C2: N=1000 4-state (headline); C4: N=256 61-state codon, split-BF16")
     ap.add_argument("--timing-steps", type=int, default=30)
     ap.add_argument("--cpu-branches", type=int, default=20,
                     help="branches of the CPU oracle sample (0 disables the CPU leg)")
@@ -189,7 +193,7 @@ def main():
                          "vs one request at a time)")
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--calls", type=int, default=10)
-    ap.add_argument("--qps-factors", default="0.5,0.9,1.5",
+    ap.add_argument("--qps-factors", default="0.25,0.5,0.75,0.9,1.2",
                     help="arrival rates as multiples of the one-at-a-time capacity")
     ap.add_argument("--budget-gb", type=float, default=32.0)
     ap.add_argument("--max-sessions", type=int, default=64)
@@ -210,9 +214,11 @@ def main():
     from paper_1905_12146_amd import binding as B
     from synth import make_workload
 
-    w = make_workload("C2")
+    if args.precision is None:
+        args.precision = "split" if args.workload == "C4" else "fp64"
+    w = make_workload(args.workload)
     N, S, m, K = w.n_tips, w.n_patterns, w.n_states, w.n_cats
-    prec = B.PG_FP64 if args.precision == "fp64" else B.PG_FP32
+    prec = {"fp64": B.PG_FP64, "fp32": B.PG_FP32, "split": B.PG_SPLIT_BF16}[args.precision]
     es = 8 if prec == B.PG_FP64 else 4
 
     dev = torch.device("cuda:0")
@@ -256,17 +262,33 @@ def main():
     achieved = bm[dom] / (avg_ms[dom] * 1e-3) / 1e9 if avg_ms[dom] > 0 else 0.0
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_record(dom, args.precision),
+                "traffic": traffic_record(dom, args.precision, args.workload),
                 "bytes_per_launch": bm[dom], "avg_us": round(avg_ms[dom] * 1e3, 2),
                 "kernels_avg_us": {k: round(v * 1e3, 2) for k, v in avg_ms.items()},
                 "eval_bytes": bm["post"] + bm["pre"],
                 "eval_frac": round((bm["post"] + bm["pre"]) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
+    if prec == B.PG_SPLIT_BF16:
+        # executed BF16 matrix-core work of the dominant kernel: 16x16x32
+        # MFMAs (16384 flops each) per tile of 16 patterns of one category;
+        # a product with a 64 x 64 matrix is 6 part products x 8 MFMAs: per
+        # internal non-root node one (post: F p); per child in the pre-order
+        # one for Q m plus one for F^T u if the child is internal
+        n_tiles = K * ((S + 15) // 16)
+        n_int = N - 2
+        mf = {"post": 48 * n_int, "pre": 48 * (2 * N - 2) + 48 * n_int}
+        fl = mf[dom] * n_tiles * 16384
+        roofline["mfma"] = {"kernel": dom, "bf16_flops_per_launch": fl,
+                            "achieved": round(fl / (avg_ms[dom] * 1e-3) / 1e12, 2), "peak": 2500.0,
+                            "unit": "TFLOP/s",
+                            "frac": round(fl / (avg_ms[dom] * 1e-3) / 1e12 / 2500.0, 4)}
+
     out = {"metric": METRIC, "value": round(value, 2), "unit": "evals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if prec == B.PG_FP64 else "f32",
-           "data": "synthetic (seeded Yule tree, random non-reversible Q, simulated sites)",
+           "dtype": {B.PG_FP64: "f64", B.PG_FP32: "f32", B.PG_SPLIT_BF16: "bf16x3-f32acc"}[prec],
+           "data": "synthetic (seeded Yule tree, random non-reversible "
+                   + ("codon " if m == 61 else "") + "Q, simulated sites)",
            "config": {"workload": f"Yule N={N}, {m}-state non-reversible CTMC, K={K} gamma(0.5) "
                                   f"categories, S={S} simulated patterns, rescaling on, "
                                   f"{len(w.t)} branch gradients",

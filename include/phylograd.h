@@ -59,9 +59,20 @@ extern "C" {
  * PG_FP32: partial vectors and their arithmetic in FP32; the transition
  *          matrices are computed in FP64 and rounded once; the per-pattern
  *          scale exponents, the site-weighted sums of logL and of the
- *          gradient stay in FP64. */
+ *          gradient stay in FP64.
+ * PG_SPLIT_BF16: partial vectors in FP32; every matrix-vector product with
+ *          a transition matrix (or with Q) runs on the BF16 matrix cores
+ *          with FP32 accumulation, each FP32 operand carried as three BF16
+ *          parts (hi + mid + lo) and the six part products of order >=
+ *          2^-16 summed; transition matrices enter as P - I.  They are
+ *          formed in FP64 from an eigen-decomposition of Q computed by
+ *          pg_set_model (scaling and squaring when Q is not usably
+ *          diagonalisable; see pg_eigensystem).  Any 2 <= n_states <= 64
+ *          (padded to 64); meant for large state spaces such as 61 codons.
+ *          No Hessian. */
 #define PG_FP64 0
 #define PG_FP32 1
+#define PG_SPLIT_BF16 2
 
 /* ---- kernels reported by pg_get_timing ------------------------------- */
 #define PG_K_PMAT  0  /* transition matrices exp(Q rate t)                     */
@@ -129,7 +140,8 @@ int pg_grad(pg_ctx* ctx, double* grad);
 
 /* Diagonal of the Hessian, d2 logL / dt_b^2, Section 2.7 Eq. (Hessian),
  * on the partials left by the last pg_logL or pg_logL_and_grad.  Also
- * returns the gradient in grad[2N-2] unless grad == NULL.  Blocks. */
+ * returns the gradient in grad[2N-2] unless grad == NULL.  Blocks.
+ * PG_E_UNSUPPORTED on a PG_SPLIT_BF16 context. */
 int pg_hessian_diag(pg_ctx* ctx, double* grad, double* hess);
 
 /* Device-pointer variant: d_t[2N-2] (FP64, device), d_logL[1] and
@@ -169,6 +181,19 @@ int64_t pg_device_bytes(const pg_ctx* ctx);
 int64_t pg_footprint_bytes(int32_t n_tips, int32_t n_patterns, int32_t n_states,
                            int32_t n_cats, int precision);
 
+/* The eigen-decomposition pg_set_model computes for a PG_SPLIT_BF16
+ * context (host only, no device needed): Q = V B V^-1 with B block diagonal,
+ * 1x1 blocks re[j] for real eigenvalues (kind[j] = 0) and, for a conjugate
+ * pair re +- i im, the 2x2 block [[re, im], [-im, re]] on columns j, j+1
+ * (kind 1, 2) that hold the real and imaginary parts of the eigenvector of
+ * re + i im.  V, Vinv: m x m row-major (caller-allocated, like re, im,
+ * kind[m]); cond = ||V||_1 ||V^-1||_1; resid = max|V B V^-1 - Q| / max|Q|.
+ * The split-BF16 kernels use it when cond <= 1e6 and resid <= 1e-11, and
+ * scaling and squaring otherwise.  PG_E_MODEL when no decomposition was
+ * found (e.g. the QR iteration did not converge). */
+int pg_eigensystem(int32_t m, const double* Q, double* V, double* Vinv, double* re, double* im,
+                   int32_t* kind, double* cond, double* resid);
+
 /* ---- serving: many gradient sessions with continuous batching --------
  *
  * A server owns a worker thread and an HBM budget.  pg_server_open creates a
@@ -187,7 +212,8 @@ int64_t pg_footprint_bytes(int32_t n_tips, int32_t n_patterns, int32_t n_states,
  * Server functions are thread-safe. */
 typedef struct pg_server pg_server;
 
-/* Errors: PG_E_INVALID (NULL, budget <= 0, max_sessions < 1), PG_E_DEVICE. */
+/* Errors: PG_E_INVALID (NULL, budget <= 0, max_sessions < 1), PG_E_DEVICE,
+ * PG_E_UNSUPPORTED (PG_SPLIT_BF16: sessions are batched FP64 / FP32 only). */
 int pg_server_create(int device, int precision, int64_t hbm_budget_bytes, int32_t max_sessions,
                      pg_server** out);
 /* Stops the worker (queued calls of admitted sessions finish first) and

@@ -30,6 +30,7 @@ PG_E_UNSUPPORTED = -9
 
 PG_FP64 = 0
 PG_FP32 = 1
+PG_SPLIT_BF16 = 2
 
 PG_K_PMAT, PG_K_POST, PG_K_ROOT, PG_K_PRE, PG_K_GSUM = range(5)
 PG_K_COUNT = 5
@@ -64,6 +65,7 @@ _SIGNATURES = [
     ("pg_get_timing", ctypes.c_int, [_vp, _vp, _vp]),
     ("pg_device_bytes", _i64, [_vp]),
     ("pg_footprint_bytes", _i64, [_i32, _i32, _i32, _i32, ctypes.c_int]),
+    ("pg_eigensystem", ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("pg_server_create", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64, _i32, ctypes.POINTER(_vp)]),
     ("pg_server_destroy", None, [_vp]),
     ("pg_server_last_error", ctypes.c_char_p, [_vp]),
@@ -229,6 +231,24 @@ def pg_device_bytes(ctx):
 
 def pg_footprint_bytes(n_tips, n_patterns, n_states, n_cats, precision=PG_FP64):
     return int(load().pg_footprint_bytes(n_tips, n_patterns, n_states, n_cats, precision))
+
+
+def pg_eigensystem(Q):
+    """(V, Vinv, re, im, kind, cond, resid) of the split-BF16 eigen route."""
+    Q = np.ascontiguousarray(Q, dtype=np.float64)
+    m = Q.shape[0]
+    V = np.zeros((m, m))
+    Vinv = np.zeros((m, m))
+    re = np.zeros(m)
+    im = np.zeros(m)
+    kind = np.zeros(m, dtype=np.int32)
+    cond = ctypes.c_double()
+    resid = ctypes.c_double()
+    code = load().pg_eigensystem(m, Q.ctypes.data, V.ctypes.data, Vinv.ctypes.data, re.ctypes.data,
+                                 im.ctypes.data, kind.ctypes.data, ctypes.byref(cond), ctypes.byref(resid))
+    if code != PG_OK:
+        raise PhyloGradError(code, "pg_eigensystem")
+    return V, Vinv, re, im, kind, cond.value, resid.value
 
 
 # -- serving -------------------------------------------------------------------

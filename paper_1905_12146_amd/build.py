@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libphylograd.so")
-SOURCES = ["kernels.hip", "capi.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "kernels_mfma.hip", "capi.cpp", "server.cpp", "eigen.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++20", "-fPIC", "--offload-arch=gfx950",
@@ -33,16 +33,21 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    from concurrent.futures import ThreadPoolExecutor
+
     tmp = os.path.join(HERE, "_build")
     os.makedirs(tmp, exist_ok=True)
+    jobs = []
     for src in SOURCES:
         obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc(), "-x", "hip", *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        jobs.append((cmd, obj))
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
+        for f in [ex.submit(subprocess.run, cmd, check=True) for cmd, _ in jobs]:
+            f.result()
+    objs = [obj for _, obj in jobs]
     tmp_out = OUT + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp_out, *objs]
     if verbose:

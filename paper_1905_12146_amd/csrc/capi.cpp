@@ -52,6 +52,13 @@ struct pg_ctx {
     int m = 0, K = 0;
     std::vector<double> Q, Q2, pi, rates, catw;
     double qnorm = 0.0;
+    // split-BF16 path: eigen-decomposition of Q padded to MP states, and Q
+    // as MFMA A operands (three BF16 parts)
+    std::vector<double> eV, eVinv, eRe, eIm;
+    std::vector<int> eKind;
+    bool expm_taylor = false;
+    double eig_cond = 0.0, eig_resid = 0.0;
+    std::vector<uint16_t> Qop;
 
     // device state
     bool dev_stale = true;        // host inputs changed since the last upload
@@ -124,7 +131,71 @@ X* buf(pg_ctx* c, const char* name) {
     return static_cast<X*>(c->bufs[name].ptr);
 }
 
-size_t elem_size(int precision) { return precision == PG_FP32 ? 4 : 8; }
+size_t elem_size(int precision) { return precision == PG_FP64 ? 8 : 4; }
+
+// BF16 bits of x, rounded to nearest even (finite x).
+uint16_t bf16_bits(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+float bf16_value(uint16_t h) {
+    const uint32_t u = (uint32_t)h << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+}
+
+// Split-BF16 model data: eigen-decomposition of Q padded to MP states (the
+// padding is identity in V and V^-1 with eigenvalue 0), and Q's MFMA A
+// operands [mt][ks][part][lane][j] in three BF16 parts, row 16 mt + lane % 16,
+// column 16 (2 ks + j / 4) + 4 (lane / 16) + j % 4 (the kernels' state order
+// of the contraction index).
+void prepare_split_model(pg_ctx* c) {
+    const int m = c->m;
+    EigenSystem es;
+    const bool ok = eigen_decompose(m, c->Q.data(), es);
+    c->eV.assign(MP * MP, 0.0);
+    c->eVinv.assign(MP * MP, 0.0);
+    c->eRe.assign(MP, 0.0);
+    c->eIm.assign(MP, 0.0);
+    c->eKind.assign(MP, 0);
+    for (int i = 0; i < MP; ++i) c->eV[i * MP + i] = c->eVinv[i * MP + i] = 1.0;
+    // one product with a V of condition up to 1e6 keeps F = P - I to about
+    // 1e-10 relative, far below what the FP32 path resolves
+    c->expm_taylor = !(ok && es.cond <= 1e6 && es.resid <= 1e-11);
+    c->eig_cond = ok ? es.cond : INFINITY;
+    c->eig_resid = ok ? es.resid : INFINITY;
+    if (!c->expm_taylor) {
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                c->eV[i * MP + j] = es.V[i * m + j];
+                c->eVinv[i * MP + j] = es.Vinv[i * m + j];
+            }
+        for (int j = 0; j < m; ++j) {
+            c->eRe[j] = es.re[j];
+            c->eIm[j] = es.im[j];
+            c->eKind[j] = es.kind[j];
+        }
+    }
+    c->Qop.assign(MF_QOP_BYTES / 2, 0);
+    for (int mt = 0; mt < 4; ++mt)
+        for (int ks = 0; ks < 2; ++ks)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < 8; ++j) {
+                    const int r = 16 * mt + lane % 16;
+                    const int y = 16 * (2 * ks + j / 4) + 4 * (lane / 16) + j % 4;
+                    const double v = (r < m && y < m) ? c->Q[r * m + y] : 0.0;
+                    const uint16_t hi = bf16_bits((float)v);
+                    const double r1 = v - (double)bf16_value(hi);
+                    const uint16_t mid = bf16_bits((float)r1);
+                    const uint16_t lo = bf16_bits((float)(r1 - (double)bf16_value(mid)));
+                    const uint16_t parts[3] = {hi, mid, lo};
+                    for (int part = 0; part < 3; ++part)
+                        c->Qop[((((mt * 2 + ks) * 3 + part) * 64 + lane) * 8) + j] = parts[part];
+                }
+}
 
 // Internal nodes grouped by height (tips have height 0); nodes of one level
 // have no ancestor relation, so a level is processed in parallel and the
@@ -213,12 +284,21 @@ int upload(pg_ctx* c) {
     const int N = c->n_tips, n_nodes = 2 * N - 1, B = n_nodes - 1;
     const int M = c->m, K = c->K;
     const size_t es = elem_size(c->precision);
+    const bool split = c->precision == PG_SPLIT_BF16;
     const int n_pb = c->S_pad / TP;
     const int n_tiles = K * n_pb;
-    const size_t vec = (size_t)K * M * c->S_pad;
+    const size_t vec = (size_t)K * (split ? MP : M) * c->S_pad;
     int r;
     if ((r = ensure_buf(c, "t", sizeof(double) * B))) return r;
-    if ((r = ensure_buf(c, "P", es * (size_t)B * K * M * M))) return r;
+    if ((r = ensure_buf(c, "P", split ? MF_SLOT_BYTES * (size_t)B * K : es * (size_t)B * K * M * M))) return r;
+    if (split) {
+        if ((r = ensure_buf(c, "eV", sizeof(double) * MP * MP))) return r;
+        if ((r = ensure_buf(c, "eVinv", sizeof(double) * MP * MP))) return r;
+        if ((r = ensure_buf(c, "eRe", sizeof(double) * MP))) return r;
+        if ((r = ensure_buf(c, "eIm", sizeof(double) * MP))) return r;
+        if ((r = ensure_buf(c, "eKind", sizeof(int) * MP))) return r;
+        if ((r = ensure_buf(c, "Qop", MF_QOP_BYTES))) return r;
+    }
     if ((r = ensure_buf(c, "msg", es * vec * (N - 1)))) return r;
     if ((r = ensure_buf(c, "qv", es * vec * (N - 1)))) return r;
     if ((r = ensure_buf(c, "codes", (size_t)N * c->S_pad))) return r;
@@ -251,7 +331,7 @@ int upload(pg_ctx* c) {
     const int H = (int)c->level_off.size() - 1;
     const int top_cap = std::min<int>(255, TOP_LDS_MAX / (int)(es * M * TP));
     int top_level = H, top_nodes = 0;
-    for (int h = H - 1; h >= 0; --h) {
+    for (int h = H - 1; h >= 0 && !split; --h) {
         const int n_h = c->level_off[h + 1] - c->level_off[h];
         if (n_h > TOP_LEVEL_MAX_NODES || top_nodes + n_h > top_cap) break;
         top_nodes += n_h;
@@ -278,6 +358,14 @@ int upload(pg_ctx* c) {
     PG_HIP(c, put("rates", c->rates.data(), sizeof(double) * K));
     PG_HIP(c, put("catw", c->catw.data(), sizeof(double) * K));
     PG_HIP(c, put("weights", c->weights.data(), sizeof(double) * c->S_pad));
+    if (split) {
+        PG_HIP(c, put("eV", c->eV.data(), sizeof(double) * MP * MP));
+        PG_HIP(c, put("eVinv", c->eVinv.data(), sizeof(double) * MP * MP));
+        PG_HIP(c, put("eRe", c->eRe.data(), sizeof(double) * MP));
+        PG_HIP(c, put("eIm", c->eIm.data(), sizeof(double) * MP));
+        PG_HIP(c, put("eKind", c->eKind.data(), sizeof(int) * MP));
+        PG_HIP(c, put("Qop", c->Qop.data(), MF_QOP_BYTES));
+    }
     // pageable host sources: make sure the copies are done before the vectors move
     PG_HIP(c, hipStreamSynchronize(st));
 
@@ -326,6 +414,15 @@ int upload(pg_ctx* c) {
     a.hess_out = buf<double>(c, "hess");
     a.logL_out = buf<double>(c, "logL");
     a.status = buf<int>(c, "status");
+    if (split) {
+        a.eV = buf<double>(c, "eV");
+        a.eVinv = buf<double>(c, "eVinv");
+        a.eRe = buf<double>(c, "eRe");
+        a.eIm = buf<double>(c, "eIm");
+        a.eKind = buf<int>(c, "eKind");
+        a.Qop = c->bufs["Qop"].ptr;
+        a.expm_taylor = c->expm_taylor ? 1 : 0;
+    }
     c->dev_stale = false;
     c->have_partials = false;
     return PG_OK;
@@ -472,8 +569,8 @@ extern "C" {
 int pg_create(int device, int precision, pg_ctx** out) {
     if (!out) return PG_E_INVALID;
     *out = nullptr;
-    if (precision != PG_FP64 && precision != PG_FP32) {
-        g_create_error = "precision must be PG_FP64 or PG_FP32";
+    if (precision != PG_FP64 && precision != PG_FP32 && precision != PG_SPLIT_BF16) {
+        g_create_error = "precision must be PG_FP64, PG_FP32 or PG_SPLIT_BF16";
         return PG_E_UNSUPPORTED;
     }
     int n = 0;
@@ -677,6 +774,7 @@ int pg_set_model(pg_ctx* c, int32_t m, const double* Q, const double* pi, int32_
         c->rates.assign(rates, rates + K);
         c->catw.assign(catw, catw + K);
         c->qnorm = qnorm;
+        if (c->precision == PG_SPLIT_BF16) prepare_split_model(c);
         c->model_set = true;
         c->dev_stale = true;
         c->have_partials = false;
@@ -741,6 +839,8 @@ int pg_logL_and_grad(pg_ctx* c, const double* t, double* logL, double* grad) {
 int pg_hessian_diag(pg_ctx* c, double* grad, double* hess) {
     if (!c) return PG_E_INVALID;
     if (!hess) return fail(c, PG_E_INVALID, "NULL hess");
+    if (c->precision == PG_SPLIT_BF16)
+        return fail(c, PG_E_UNSUPPORTED, "the Hessian diagonal has no split-BF16 kernel");
     if (!c->have_partials || c->dev_stale)
         return fail(c, PG_E_STATE, "no resident partials: call pg_logL first");
     return guarded(c, [&] {
@@ -832,18 +932,39 @@ int64_t pg_device_bytes(const pg_ctx* c) {
 
 int64_t pg_footprint_bytes(int32_t N, int32_t S, int32_t m, int32_t K, int precision) {
     if (N < 2 || S < 1 || m < 2 || K < 1) return -1;
-    const int64_t es = precision == PG_FP32 ? 4 : 8;
+    const bool split = precision == PG_SPLIT_BF16;
+    const int64_t es = precision == PG_FP64 ? 8 : 4;
     const int64_t S_pad = (S + TP - 1) / TP * TP;
     const int64_t B = 2 * (int64_t)N - 2;
     const int64_t n_tiles = K * (S_pad / TP);
+    const int64_t ms = split ? MP : m;
     int64_t tot = 0;
-    tot += 2 * es * (int64_t)K * m * S_pad * (N - 1);       // msg + qv
-    tot += es * B * K * m * m;                             // P
+    tot += 2 * es * (int64_t)K * ms * S_pad * (N - 1);      // msg + qv
+    tot += split ? (int64_t)MF_SLOT_BYTES * B * K : es * B * K * m * m;  // P
     tot += (int64_t)N * S_pad;                             // codes
     tot += 8 * (n_tiles * B + (S_pad / TP) * B);           // tile partial sums
     tot += (8 + 8 + 4) * (int64_t)K * S_pad + 8 * S_pad;   // root values, rho, weights
     tot += 8 * 4 * B + 4 * 3 * (int64_t)N + 4096;          // t, grad, hess, schedule
     return tot;
+}
+
+int pg_eigensystem(int32_t m, const double* Q, double* V, double* Vinv, double* re, double* im, int32_t* kind,
+                   double* cond, double* resid) {
+    if (!Q || !V || !Vinv || !re || !im || !kind || !cond || !resid || m < 1 || m > 4096) return PG_E_INVALID;
+    try {
+        EigenSystem es;
+        if (!eigen_decompose(m, Q, es)) return PG_E_MODEL;
+        std::copy(es.V.begin(), es.V.end(), V);
+        std::copy(es.Vinv.begin(), es.Vinv.end(), Vinv);
+        std::copy(es.re.begin(), es.re.end(), re);
+        std::copy(es.im.begin(), es.im.end(), im);
+        for (int j = 0; j < m; ++j) kind[j] = es.kind[j];
+        *cond = es.cond;
+        *resid = es.resid;
+        return PG_OK;
+    } catch (...) {
+        return PG_E_OOM;
+    }
 }
 
 }  // extern "C"

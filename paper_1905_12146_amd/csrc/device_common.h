@@ -1,0 +1,138 @@
+// Device helpers shared by the kernels of every precision: exact power-of-
+// two rescaling, DPP row reductions, tip codes, the level schedule, and the
+// per-site likelihood from the per-category root values.
+#pragma once
+
+#include <climits>
+
+#include "pg_internal.h"
+
+namespace pg {
+
+__device__ inline int exp_of(double x) { int e; (void)frexp(x, &e); return e; }
+__device__ inline int exp_of(float x) { int e; (void)frexpf(x, &e); return e; }
+__device__ inline double pow2_scale(double x, int e) { return ldexp(x, e); }
+__device__ inline float pow2_scale(float x, int e) { return ldexpf(x, e); }
+
+// Sum over the 16 lanes of a node slot (one DPP row).  Each step adds the
+// row rotated by 1, 2, 4, 8 lanes (v_mov_b32_dpp row_ror on both halves of
+// the double), so every lane ends with the full row sum; callers use lane 0's
+// value, whose association order is fixed.
+template <int N>
+__device__ inline double row_ror(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x120 + N, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x120 + N, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ inline double sum16(double v) {
+    v += row_ror<1>(v);
+    v += row_ror<2>(v);
+    v += row_ror<4>(v);
+    v += row_ror<8>(v);
+    return v;
+}
+
+__device__ inline unsigned long long tip_mask(const EvalArgs& a, unsigned code, int M) {
+    if (code < (unsigned)M) return 1ull << code;
+    if (code == 255u) return ~0ull;
+    return a.masks[code];
+}
+
+// Level-ordered schedule entry idx: {node, child 0, child 1, 0}, from LDS
+// when the schedule was staged there.
+__device__ inline int4 sched_at(const EvalArgs& a, const int4* lds, int idx) {
+    return a.sched_lds ? lds[idx] : a.sched[idx];
+}
+
+__device__ inline void stage_schedule(const EvalArgs& a, int4* lds) {
+    if (a.sched_lds) {
+        const int n = a.n_tips - 1;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = a.sched[i];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- per-site likelihood
+//
+// L_s = sum_l w_l L~_{s,l} 2^{E_{s,l}}  (Eq. discreteRateLikelihood), formed
+// relative to the largest exponent so nothing under- or overflows.
+
+struct SiteLik {
+    double scaled;  // L_s 2^-emax
+    int emax;
+    bool nan;
+};
+
+__device__ inline SiteLik site_likelihood(const EvalArgs& a, int s) {
+    SiteLik r{0.0, INT_MIN, false};
+    for (int l = 0; l < a.K; ++l) {
+        const double L = a.rootL[(size_t)l * a.S_pad + s];
+        if (isnan(L)) r.nan = true;
+        if (L > 0.0) r.emax = max(r.emax, a.rootE[(size_t)l * a.S_pad + s]);
+    }
+    if (r.emax != INT_MIN)
+        for (int l = 0; l < a.K; ++l) {
+            const double L = a.rootL[(size_t)l * a.S_pad + s];
+            if (L > 0.0) r.scaled += a.catw[l] * ldexp(L, a.rootE[(size_t)l * a.S_pad + s] - r.emax);
+        }
+    return r;
+}
+
+// logL = sum_s w_s log L_s in one fixed order, shared by every path:
+//   part[pb] = butterfly sum over the TP patterns of block pb (sum16),
+//   logL     = fixed reduction of part[0..n_pb) (finish_logl).
+// site_log_term gives one pattern's term and status flag.
+__device__ inline double site_log_term(const EvalArgs& a, int s, const SiteLik& r, int& flag) {
+    const double LN2 = 0.69314718055994530942;
+    const double w = a.weights[s];
+    flag = 0;
+    if (r.nan) { flag = 1; return 0.0; }
+    if (r.scaled > 0.0) return (w > 0.0) ? w * (log(r.scaled) + (double)r.emax * LN2) : 0.0;
+    if (w > 0.0) flag = 2;
+    return 0.0;
+}
+
+__device__ inline int or16(int v) {
+    v |= __builtin_amdgcn_mov_dpp(v, 0x121, 0xf, 0xf, false);
+    v |= __builtin_amdgcn_mov_dpp(v, 0x122, 0xf, 0xf, false);
+    v |= __builtin_amdgcn_mov_dpp(v, 0x124, 0xf, 0xf, false);
+    v |= __builtin_amdgcn_mov_dpp(v, 0x128, 0xf, 0xf, false);
+    return v;
+}
+
+// One 16-lane row computes part[pb] (all lanes of the row active).
+__device__ inline void logl_block_part(const EvalArgs& a, int pb, int ps, const SiteLik& r) {
+    int flag;
+    double v = site_log_term(a, pb * TP + ps, r, flag);
+    v = sum16(v);
+    flag = or16(flag);
+    if (ps == 0) {
+        a.logl_part[pb] = v;
+        a.flag_part[pb] = flag;
+    }
+}
+
+// Per-lane coefficients of pattern s in category l:
+//   g = w_s rho_{s,l} gamma_l      (gradient)
+//   nw = rho_{s,l} gamma_l         (per-site gradient part, Hessian)
+//   h = w_s rho_{s,l} gamma_l^2    (second-derivative part, Hessian)
+// with rho_{s,l} = w_l L_{s,l} / L_s from the root values.
+struct Coef {
+    double g, nw, h;
+};
+
+__device__ inline Coef coef_of(const EvalArgs& a, int l, int s, const SiteLik& r) {
+    Coef cf{0.0, 0.0, 0.0};
+    const double L = a.rootL[(size_t)l * a.S_pad + s];
+    if (!r.nan && r.scaled > 0.0 && L > 0.0) {
+        const double rho = a.catw[l] * ldexp(L, a.rootE[(size_t)l * a.S_pad + s] - r.emax) / r.scaled;
+        cf.nw = rho * a.rates[l];
+        cf.g = a.weights[s] * cf.nw;
+        cf.h = cf.g * a.rates[l];
+    }
+    return cf;
+}
+
+}  // namespace pg

@@ -24,39 +24,13 @@
 //   rho_{s,l} = w_l L_{s,l} / L_s,
 // which equals Eq. (GradientWithGamma) of Section 2.6: u^T m is L_{s,l} up
 // to the category's own scale factor, which cancels in each ratio.
-#include "pg_internal.h"
+#include "device_common.h"
 
-#include <climits>
 #include <utility>
 
 namespace pg {
 
 // ---------------------------------------------------------------- helpers
-
-__device__ inline int exp_of(double x) { int e; (void)frexp(x, &e); return e; }
-__device__ inline int exp_of(float x) { int e; (void)frexpf(x, &e); return e; }
-__device__ inline double pow2_scale(double x, int e) { return ldexp(x, e); }
-__device__ inline float pow2_scale(float x, int e) { return ldexpf(x, e); }
-
-// Sum over the 16 lanes of a node slot (one DPP row).  Each step adds the
-// row rotated by 1, 2, 4, 8 lanes (v_mov_b32_dpp row_ror on both halves of
-// the double), so every lane ends with the full row sum; callers use lane 0's
-// value, whose association order is fixed.
-template <int N>
-__device__ inline double row_ror(double v) {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x120 + N, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x120 + N, 0xf, 0xf, false);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-
-__device__ inline double sum16(double v) {
-    v += row_ror<1>(v);
-    v += row_ror<2>(v);
-    v += row_ror<4>(v);
-    v += row_ror<8>(v);
-    return v;
-}
 
 __device__ inline size_t vec_off(const EvalArgs& a, int node, int tile, int M) {
     return ((size_t)(node - a.n_tips) * a.n_tiles + tile) * (size_t)(M * TP);
@@ -157,12 +131,6 @@ __device__ inline double pientry(const EvalArgs& a, int x) {
     else return a.pi64[x];
 }
 
-__device__ inline unsigned long long tip_mask(const EvalArgs& a, unsigned code, int M) {
-    if (code < (unsigned)M) return 1ull << code;
-    if (code == 255u) return ~0ull;
-    return a.masks[code];
-}
-
 // Outgoing message of child c for category l, pattern s: the stored
 // P_c p~_c of an internal child; for a tip, P_c times the tip indicator
 // (Section 2.1): the column of the observed state, or the sum of the allowed
@@ -230,20 +198,6 @@ __device__ inline void child_finish(const EvalArgs& a, int c, int l, const Child
     } else {
 #pragma unroll
         for (int x = 0; x < M; ++x) out[x] = r.v[x];
-    }
-}
-
-// Level-ordered schedule entry idx: {node, child 0, child 1, 0}, from LDS
-// when the schedule was staged there.
-__device__ inline int4 sched_at(const EvalArgs& a, const int4* lds, int idx) {
-    return a.sched_lds ? lds[idx] : a.sched[idx];
-}
-
-__device__ inline void stage_schedule(const EvalArgs& a, int4* lds) {
-    if (a.sched_lds) {
-        const int n = a.n_tips - 1;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = a.sched[i];
-        __syncthreads();
     }
 }
 
@@ -515,66 +469,6 @@ __device__ inline void post_body(const EvalArgs& a, int tile, int4* lds_sched) {
     }
 }
 
-// ---------------------------------------------------------------- per-site likelihood
-//
-// L_s = sum_l w_l L~_{s,l} 2^{E_{s,l}}  (Eq. discreteRateLikelihood), formed
-// relative to the largest exponent so nothing under- or overflows.
-
-struct SiteLik {
-    double scaled;  // L_s 2^-emax
-    int emax;
-    bool nan;
-};
-
-__device__ inline SiteLik site_likelihood(const EvalArgs& a, int s) {
-    SiteLik r{0.0, INT_MIN, false};
-    for (int l = 0; l < a.K; ++l) {
-        const double L = a.rootL[(size_t)l * a.S_pad + s];
-        if (isnan(L)) r.nan = true;
-        if (L > 0.0) r.emax = max(r.emax, a.rootE[(size_t)l * a.S_pad + s]);
-    }
-    if (r.emax != INT_MIN)
-        for (int l = 0; l < a.K; ++l) {
-            const double L = a.rootL[(size_t)l * a.S_pad + s];
-            if (L > 0.0) r.scaled += a.catw[l] * ldexp(L, a.rootE[(size_t)l * a.S_pad + s] - r.emax);
-        }
-    return r;
-}
-
-// logL = sum_s w_s log L_s in one fixed order, shared by every path:
-//   part[pb] = butterfly sum over the TP patterns of block pb (sum16),
-//   logL     = fixed reduction of part[0..n_pb) (finish_logl).
-// site_log_term gives one pattern's term and status flag.
-__device__ inline double site_log_term(const EvalArgs& a, int s, const SiteLik& r, int& flag) {
-    const double LN2 = 0.69314718055994530942;
-    const double w = a.weights[s];
-    flag = 0;
-    if (r.nan) { flag = 1; return 0.0; }
-    if (r.scaled > 0.0) return (w > 0.0) ? w * (log(r.scaled) + (double)r.emax * LN2) : 0.0;
-    if (w > 0.0) flag = 2;
-    return 0.0;
-}
-
-__device__ inline int or16(int v) {
-    v |= __builtin_amdgcn_mov_dpp(v, 0x121, 0xf, 0xf, false);
-    v |= __builtin_amdgcn_mov_dpp(v, 0x122, 0xf, 0xf, false);
-    v |= __builtin_amdgcn_mov_dpp(v, 0x124, 0xf, 0xf, false);
-    v |= __builtin_amdgcn_mov_dpp(v, 0x128, 0xf, 0xf, false);
-    return v;
-}
-
-// One 16-lane row computes part[pb] (all lanes of the row active).
-__device__ inline void logl_block_part(const EvalArgs& a, int pb, int ps, const SiteLik& r) {
-    int flag;
-    double v = site_log_term(a, pb * TP + ps, r, flag);
-    v = sum16(v);
-    flag = or16(flag);
-    if (ps == 0) {
-        a.logl_part[pb] = v;
-        a.flag_part[pb] = flag;
-    }
-}
-
 template <int NT>
 __device__ void finish_logl(const EvalArgs& a) {
     double acc = 0.0;
@@ -624,14 +518,6 @@ __global__ void __launch_bounds__(LOGL_THREADS) logl_kernel(EvalArgs a) {
 //   q_a = P_a^T u_a, rescaled, stored if a is internal   Eq. (preOrderUpdate)
 // The numerator uses Q m_a = Q P_a p_a = P_a Q p_a, so q_a^T Q p_a is
 // u_a^T Q m_a.
-
-// Per-lane coefficients of pattern s in category l:
-//   g = w_s rho_{s,l} gamma_l      (gradient)
-//   nw = rho_{s,l} gamma_l         (per-site gradient part, Hessian)
-//   h = w_s rho_{s,l} gamma_l^2    (second-derivative part, Hessian)
-struct Coef {
-    double g, nw, h;
-};
 
 // HESS adds, for Eq. (Hessian) of Section 2.7 per site:
 //   tile sum of w_s rho gamma^2 (u^T Q^2 m)/(u^T m)   -> partial2[tile][c]
@@ -767,16 +653,10 @@ __device__ inline void pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
     const int ps = threadIdx.x % TP, ns = threadIdx.x / TP;
     const int s = pb * TP + ps;
     // rho_{s,l} gamma_l w_s from the per-category root values
-    Coef cf{0.0, 0.0, 0.0};
+    Coef cf;
     {
         const SiteLik r = site_likelihood(a, s);
-        const double L = a.rootL[(size_t)l * a.S_pad + s];
-        if (!r.nan && r.scaled > 0.0 && L > 0.0) {
-            const double rho = a.catw[l] * ldexp(L, a.rootE[(size_t)l * a.S_pad + s] - r.emax) / r.scaled;
-            cf.nw = rho * a.rates[l];
-            cf.g = a.weights[s] * cf.nw;
-            cf.h = cf.g * a.rates[l];
-        }
+        cf = coef_of(a, l, s, r);
         // the category-0 tile of each pattern block also forms its logL part
         if (l == 0 && ns == 0) logl_block_part(a, pb, ps, r);
     }
@@ -960,6 +840,7 @@ __global__ void __launch_bounds__(GS_THREADS) gsum_batch(const EvalArgs* __restr
 // ---------------------------------------------------------------- dispatch
 
 bool kernel_supported(int M, int precision) {
+    if (precision == PG_SPLIT_BF16) return M >= 2 && M <= MP;
     return (M == 4 || M == 20) && (precision == PG_FP64 || precision == PG_FP32);
 }
 
@@ -984,6 +865,7 @@ static hipError_t pmat_launch(const EvalArgs& a, hipStream_t st) {
     } while (0)
 
 hipError_t launch_pmat(const EvalArgs& a, int precision, hipStream_t st) {
+    if (precision == PG_SPLIT_BF16) return launch_mfma_pmat(a, st);
     PG_DISPATCH(pmat_launch, a, st);
 }
 
@@ -994,6 +876,7 @@ static hipError_t post_launch(const EvalArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_post(const EvalArgs& a, int precision, hipStream_t st) {
+    if (precision == PG_SPLIT_BF16) return launch_mfma_post(a, st);
     PG_DISPATCH(post_launch, a, st);
 }
 
@@ -1011,6 +894,7 @@ static hipError_t pre_launch(const EvalArgs& a, hipStream_t st, bool hess) {
 }
 
 hipError_t launch_pre(const EvalArgs& a, int precision, hipStream_t st, bool hess) {
+    if (precision == PG_SPLIT_BF16) return hess ? hipErrorInvalidValue : launch_mfma_pre(a, st);
     PG_DISPATCH(pre_launch, a, st, hess);
 }
 

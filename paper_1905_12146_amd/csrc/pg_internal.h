@@ -71,9 +71,26 @@ struct EvalArgs {
     double* logL_out;                  // [1] logL destination
     int* status;                       // [1] written by each logL reduction: 0 ok,
                                        //     1 NaN (bad length), 2 zero likelihood
+    // split-BF16 path: states padded to MP, P holds per-(branch, category)
+    // operand slots of MF_SLOT_BYTES, msg/qv hold MP x TP FP32 per tile
+    const double* eV;                  // [MP][MP] V of Q = V B V^-1, identity on padding
+    const double* eVinv;               // [MP][MP]
+    const double* eRe;                 // [MP] eigenvalue real parts
+    const double* eIm;                 // [MP] imaginary parts of pairs
+    const int* eKind;                  // [MP] 0 real, 1 / 2 the two columns of a pair
+    int expm_taylor;                   // 1: scaling and squaring (Q not usably diagonalisable)
+    const void* Qop;                   // Q as MFMA A operands, three BF16 parts
 };
 
-enum Precision { FP64 = PG_FP64, FP32 = PG_FP32 };
+enum Precision { FP64 = PG_FP64, FP32 = PG_FP32, SPLIT_BF16 = PG_SPLIT_BF16 };
+
+// Split-BF16 path: padded state count, bytes of one (branch, category)
+// operand slot (A operands of P - I and P^T - I in three BF16 parts for an
+// internal branch, the FP32 tip table of P for a tip branch), and bytes of
+// Q's A operands.
+constexpr int MP = 64;
+constexpr size_t MF_SLOT_BYTES = 49152;
+constexpr size_t MF_QOP_BYTES = 3 * 8 * 64 * 16;
 
 // Kernel launchers (kernels.hip).  Each returns a hipError_t from the launch.
 bool kernel_supported(int M, int precision);
@@ -84,6 +101,12 @@ hipError_t launch_post(const EvalArgs& a, int precision, hipStream_t s);
 hipError_t launch_logl(const EvalArgs& a, hipStream_t s);
 hipError_t launch_pre(const EvalArgs& a, int precision, hipStream_t s, bool hess);
 hipError_t launch_hsum(const EvalArgs& a, hipStream_t s);
+// split-BF16 launchers (kernels_mfma.hip)
+hipError_t launch_mfma_pmat(const EvalArgs& a, hipStream_t s);
+hipError_t launch_mfma_post(const EvalArgs& a, hipStream_t s);
+hipError_t launch_mfma_pre(const EvalArgs& a, hipStream_t s);
+size_t mfma_post_lds_bytes(const EvalArgs& a);
+size_t mfma_pre_lds_bytes(const EvalArgs& a);
 
 // One continuous-batching step: every request's pmat, post, pre and gsum
 // blocks in one launch each.  reqs and the maps are device arrays; map
@@ -103,6 +126,18 @@ int gsum_total_blocks(const EvalArgs& a);
 size_t post_lds_bytes(const EvalArgs& a);
 size_t pre_lds_bytes(const EvalArgs& a, int precision);
 hipError_t launch_batch(const BatchLaunch& b, hipStream_t s);
+
+// Q = V B V^-1 with B block diagonal (eigen.cpp).  kind[j]: 0 real
+// eigenvalue re[j]; 1 and 2 the two columns (real and imaginary part of the
+// eigenvector of re + i im) of a conjugate pair.  Row-major m x m.
+struct EigenSystem {
+    int m = 0;
+    std::vector<double> V, Vinv, re, im;
+    std::vector<int> kind;
+    double cond = 0.0;   // ||V||_1 ||V^-1||_1
+    double resid = 0.0;  // max |V B V^-1 - Q| / max |Q|
+};
+bool eigen_decompose(int m, const double* Q, EigenSystem& es);
 
 // Device memory source of a context (the serving scheduler's pool).
 struct DeviceAllocator {

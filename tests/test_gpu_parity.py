@@ -180,3 +180,36 @@ def test_zero_likelihood(gpu):
         ctx.set_patterns(masks, np.array([0.0, 2.0]), 4)
         logL, g = ctx.logL_and_grad(np.zeros(2))
         assert math.isfinite(logL)
+
+
+# Extreme tree shapes: a balanced tree (every tip in a cherry, i.e. an
+# internal node whose children are both tips), a caterpillar (one cherry,
+# one node per level) and a cherry directly under the root.
+_SHAPES = {
+    "balanced8": [8, 8, 9, 9, 11, 11, 12, 12, 10, 10, 14, 13, 13, 14, -1],
+    "caterpillar6": [6, 6, 7, 8, 9, 10, 7, 8, 9, 10, -1],
+    "root_cherry3": [3, 3, 4, 4, -1],
+}
+
+
+@pytest.mark.parametrize("shape", sorted(_SHAPES))
+@pytest.mark.parametrize("precision,tol", [(B.PG_FP64, TOL64), (B.PG_FP32, TOL32)])
+def test_tree_shapes(gpu, shape, precision, tol):
+    parent = np.array(_SHAPES[shape], dtype=np.int32)
+    n = (len(parent) + 1) // 2
+    w = small(n_tips=n, n_patterns=37, n_cats=2, ambiguous=0.1, seed=n + 1)
+    w.parent = parent
+    check(w, precision, tol)
+
+
+def test_tree_shapes_hessian(gpu):
+    parent = np.array(_SHAPES["balanced8"], dtype=np.int32)
+    w = small(n_tips=8, n_patterns=37, n_cats=2, ambiguous=0.1, seed=3)
+    w.parent = parent
+    with B.Context(0, B.PG_FP64) as ctx:
+        ctx.set_workload(w)
+        ctx.logL(w.t)
+        grad, hess = ctx.hessian_diag()
+    r = O.linear_gradient(*args_of(w))
+    assert np.all(np.abs(grad - r["grad"]) <= TOL64 * r["abs_grad"])
+    assert np.all(np.abs(hess - r["hess"]) <= TOL64 * r["abs_hess"])

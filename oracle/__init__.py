@@ -30,5 +30,5 @@ from .brute import brute_site_likelihoods, brute_gradient  # noqa: F401
 from .pruning import site_log_likelihoods, log_likelihood  # noqa: F401
 from .naive import naive_gradient, naive_hessian_diag  # noqa: F401
 from .linear import linear_gradient, linear_partials  # noqa: F401
-from .fd import central_fd_gradient  # noqa: F401
+from .fd import central_fd_gradient, richardson_directional  # noqa: F401
 from .compare import parity_report  # noqa: F401

@@ -50,14 +50,19 @@ class Tree:
 
 @dataclasses.dataclass
 class Model:
-    Q: np.ndarray            # [m, m], Q[x, y] = rate parent x -> child y
+    Q: np.ndarray            # [m, m], Q[x, y] = rate parent x -> child y; or
+                             # [2N-2, m, m], the rate matrix of each branch
     pi: np.ndarray           # [m]
     rates: np.ndarray        # [K] gamma_l
     cat_weights: np.ndarray  # [K] Pr(gamma_l)
 
     @property
     def m(self) -> int:
-        return self.Q.shape[0]
+        return self.Q.shape[-1]
+
+    def Q_of(self, b: int) -> np.ndarray:
+        """Rate matrix on branch b (the branch above node b)."""
+        return self.Q[b] if self.Q.ndim == 3 else self.Q
 
 
 def make_tree(parent) -> Tree:
@@ -96,15 +101,21 @@ def validate(parent, t, Q, pi, rates, cat_weights, masks, weights):
     """Check every input; return (Tree, Model, indicator tips [N, S, m])."""
     tree = make_tree(parent)
     Q = np.asarray(Q, dtype=np.float64)
-    m = Q.shape[0]
-    if Q.shape != (m, m) or m < 2:
+    m = Q.shape[-1]
+    if Q.ndim == 3:
+        # a non-homogeneous model: one rate matrix per branch (Section 2.1
+        # allows the CTMC to differ between branches)
+        if Q.shape != (tree.n_nodes - 1, m, m) or m < 2:
+            raise OracleInputError("per-branch Q must be [2N-2, m, m]")
+    elif Q.shape != (m, m) or m < 2:
         raise OracleInputError("Q must be square with m >= 2")
-    off = Q - np.diag(np.diag(Q))
-    if (off < 0).any():
-        raise OracleInputError("off-diagonal rates must be non-negative")
-    scale = max(np.abs(Q).max(), 1.0)
-    if np.abs(Q.sum(axis=1)).max() > 1e-12 * scale * m:
-        raise OracleInputError("rows of Q must sum to zero")
+    for Qb in (Q if Q.ndim == 3 else [Q]):
+        off = Qb - np.diag(np.diag(Qb))
+        if (off < 0).any():
+            raise OracleInputError("off-diagonal rates must be non-negative")
+        scale = max(np.abs(Qb).max(), 1.0)
+        if np.abs(Qb.sum(axis=1)).max() > 1e-12 * scale * m:
+            raise OracleInputError("rows of Q must sum to zero")
     pi = np.asarray(pi, dtype=np.float64)
     if pi.shape != (m,) or (pi < 0).any() or abs(pi.sum() - 1.0) > 1e-12:
         raise OracleInputError("pi must be a probability vector")

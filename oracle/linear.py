@@ -80,15 +80,15 @@ def linear_gradient(parent, t, Q, pi, rates, cat_weights, masks, weights):
     Ltil = np.einsum("l,lsx,lsx->s", model.cat_weights, p[root], q[root])
     logLs = np.log(Ltil) + lsp[root]
     logL = math.fsum(np.where(w > 0, w * logLs, 0.0).tolist())
-    Q2 = model.Q @ model.Q
     B = tree.n_nodes - 1
     grad, absg, hess, absh = np.zeros(B), np.zeros(B), np.zeros(B), np.zeros(B)
     g1 = model.rates * model.cat_weights
     g2 = model.rates ** 2 * model.cat_weights
     for i in range(B):
-        # p^T Q^T q = q^T Q p, per category and site
-        Qp = np.matmul(p[i], model.Q.T)
-        Q2p = np.matmul(p[i], Q2.T)
+        # p^T Q_i^T q = q^T Q_i p, per category and site (Q_i: branch i's matrix)
+        Qi = model.Q_of(i)
+        Qp = np.matmul(p[i], Qi.T)
+        Q2p = np.matmul(p[i], (Qi @ Qi).T)
         den = np.einsum("l,lsx,lsx->s", model.cat_weights, q[i], p[i])
         num = np.einsum("l,lsx,lsx->s", g1, q[i], Qp)
         num2 = np.einsum("l,lsx,lsx->s", g2, q[i], Q2p)

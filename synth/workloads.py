@@ -384,3 +384,15 @@ def request_workload(spec: RequestSpec) -> Workload:
 def perturb_lengths(t: np.ndarray, rng: np.random.Generator, scale: float = 0.01) -> np.ndarray:
     """Next branch lengths of a request: t * exp(scale * N(0, 1))."""
     return t * np.exp(scale * rng.normal(size=t.shape))
+
+
+def branch_models(workload: Workload, n_models: int, seed: int = 0):
+    """A non-homogeneous model for a workload: n_models random non-reversible
+    rate matrices (the first is the workload's Q) and a model index per
+    branch, uniform over the models.  Returns (Qs [n_models, m, m],
+    model_of_branch int32 [2N-2])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = workload.n_states
+    Qs = [workload.Q] + [random_rate_matrix(m, rng) for _ in range(n_models - 1)]
+    model = rng.integers(0, n_models, size=len(workload.t)).astype(np.int32)
+    return np.stack(Qs), model

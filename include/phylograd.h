@@ -123,6 +123,17 @@ int pg_set_model(pg_ctx* ctx, int32_t n_states, const double* Q,
                  const double* root_freqs, int32_t n_cats,
                  const double* cat_rates, const double* cat_weights);
 
+/* Non-homogeneous model (Section 2.1: the process may differ between
+ * branches): branch b (the branch above node b) evolves under rate matrix
+ * Q[model_of_branch[b]], Q[n_models*m*m] row-major generators checked as by
+ * pg_set_model; root_freqs and the rate categories stay those of
+ * pg_set_model.  The gradient and Hessian use each branch's own matrix.
+ * Both arrays are copied.  n_models = 0 returns to the homogeneous model.
+ * Cleared by pg_set_tree with a different N or pg_set_model with a
+ * different m.  Errors: PG_E_STATE (no tree or model), PG_E_INVALID (NULL,
+ * index out of range), PG_E_MODEL, PG_E_UNSUPPORTED (PG_SPLIT_BF16). */
+int pg_set_branch_models(pg_ctx* ctx, int32_t n_models, const double* Q, const int32_t* model_of_branch);
+
 /* One evaluation from host memory: t[2N-2] branch lengths in, *logL and,
  * unless grad == NULL, grad[2N-2] = dlogL/dt_b out.  Blocks until done.
  * Errors: PG_E_STATE, PG_E_INVALID (t), PG_E_ZERO_LIK (*logL = -inf, grad

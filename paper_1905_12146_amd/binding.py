@@ -54,6 +54,7 @@ _SIGNATURES = [
     ("pg_set_tree", ctypes.c_int, [_vp, _i32, _vp]),
     ("pg_set_patterns", ctypes.c_int, [_vp, _i32, _i32, _vp, _vp]),
     ("pg_set_model", ctypes.c_int, [_vp, _i32, _vp, _vp, _i32, _vp, _vp]),
+    ("pg_set_branch_models", ctypes.c_int, [_vp, _i32, _vp, _vp]),
     ("pg_logL_and_grad", ctypes.c_int, [_vp, _vp, _vp, _vp]),
     ("pg_logL", ctypes.c_int, [_vp, _vp, _vp]),
     ("pg_grad", ctypes.c_int, [_vp, _vp]),
@@ -160,6 +161,18 @@ def pg_set_model(ctx, Q, pi, rates, cat_weights):
         raise PhyloGradError(PG_E_INVALID, "Q [m, m], pi [m], rates and weights [K] expected")
     _check(ctx, load().pg_set_model(ctx, Q.shape[0], _ptr(Q), _ptr(pi), len(rates), _ptr(rates),
                                     _ptr(cat_weights)))
+
+
+def pg_set_branch_models(ctx, Qs, model_of_branch):
+    """Qs [n_models, m, m] and model_of_branch [2N-2]; Qs = None clears."""
+    if Qs is None:
+        _check(ctx, load().pg_set_branch_models(ctx, 0, None, None))
+        return
+    Qs = np.ascontiguousarray(Qs, dtype=np.float64)
+    model = np.ascontiguousarray(model_of_branch, dtype=np.int32)
+    if Qs.ndim != 3 or Qs.shape[1] != Qs.shape[2] or model.ndim != 1:
+        raise PhyloGradError(PG_E_INVALID, "Qs [n_models, m, m] and model_of_branch [2N-2] expected")
+    _check(ctx, load().pg_set_branch_models(ctx, Qs.shape[0], _ptr(Qs), model.ctypes.data))
 
 
 def _lengths(t, n_branches):
@@ -355,6 +368,11 @@ class Context:
 
     def set_model(self, Q, pi, rates, cat_weights):
         pg_set_model(self.handle, Q, pi, rates, cat_weights)
+
+    def set_branch_models(self, Qs, model_of_branch):
+        if Qs is not None and len(model_of_branch) != (self.n_branches or 0):
+            raise PhyloGradError(PG_E_INVALID, f"model_of_branch needs {self.n_branches} entries")
+        pg_set_branch_models(self.handle, Qs, model_of_branch)
 
     def set_stream(self, stream_handle):
         pg_set_stream(self.handle, stream_handle)

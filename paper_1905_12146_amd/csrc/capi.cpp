@@ -59,6 +59,10 @@ struct pg_ctx {
     bool expm_taylor = false;
     double eig_cond = 0.0, eig_resid = 0.0;
     std::vector<uint16_t> Qop;
+    // non-homogeneous model: branch b uses bm_Q[bm_model[b]] (bm_n = 0: off)
+    int bm_n = 0;
+    std::vector<double> bm_Q, bm_Q2, bm_qnorm;
+    std::vector<int> bm_model;
 
     // device state
     bool dev_stale = true;        // host inputs changed since the last upload
@@ -321,6 +325,12 @@ int upload(pg_ctx* c) {
     if ((r = ensure_buf(c, "hess", sizeof(double) * B))) return r;
     if ((r = ensure_buf(c, "logL", sizeof(double) * 2))) return r;
     if ((r = ensure_buf(c, "status", sizeof(int) * 2))) return r;
+    if (c->bm_n > 0) {
+        if ((r = ensure_buf(c, "bm_Q", sizeof(double) * c->bm_Q.size()))) return r;
+        if ((r = ensure_buf(c, "bm_Q2", sizeof(double) * c->bm_Q2.size()))) return r;
+        if ((r = ensure_buf(c, "bm_qnorm", sizeof(double) * c->bm_qnorm.size()))) return r;
+        if ((r = ensure_buf(c, "bm_model", sizeof(int) * c->bm_model.size()))) return r;
+    }
 
     hipStream_t st = c->stream;
     auto put = [&](const char* name, const void* src, size_t bytes) {
@@ -358,6 +368,12 @@ int upload(pg_ctx* c) {
     PG_HIP(c, put("rates", c->rates.data(), sizeof(double) * K));
     PG_HIP(c, put("catw", c->catw.data(), sizeof(double) * K));
     PG_HIP(c, put("weights", c->weights.data(), sizeof(double) * c->S_pad));
+    if (c->bm_n > 0) {
+        PG_HIP(c, put("bm_Q", c->bm_Q.data(), sizeof(double) * c->bm_Q.size()));
+        PG_HIP(c, put("bm_Q2", c->bm_Q2.data(), sizeof(double) * c->bm_Q2.size()));
+        PG_HIP(c, put("bm_qnorm", c->bm_qnorm.data(), sizeof(double) * c->bm_qnorm.size()));
+        PG_HIP(c, put("bm_model", c->bm_model.data(), sizeof(int) * c->bm_model.size()));
+    }
     if (split) {
         PG_HIP(c, put("eV", c->eV.data(), sizeof(double) * MP * MP));
         PG_HIP(c, put("eVinv", c->eVinv.data(), sizeof(double) * MP * MP));
@@ -414,6 +430,13 @@ int upload(pg_ctx* c) {
     a.hess_out = buf<double>(c, "hess");
     a.logL_out = buf<double>(c, "logL");
     a.status = buf<int>(c, "status");
+    a.n_models = c->bm_n;
+    if (c->bm_n > 0) {
+        a.Qm = buf<double>(c, "bm_Q");
+        a.Q2m = buf<double>(c, "bm_Q2");
+        a.qnorm_m = buf<double>(c, "bm_qnorm");
+        a.branch_model = buf<int>(c, "bm_model");
+    }
     if (split) {
         a.eV = buf<double>(c, "eV");
         a.eVinv = buf<double>(c, "eVinv");
@@ -648,7 +671,10 @@ int pg_set_tree(pg_ctx* c, int32_t N, const int32_t* parent) {
     return guarded(c, [&] {
         int r = check_tree(c, N, parent);
         if (r) return r;
-        if (c->n_tips != N) c->patterns_set = false;
+        if (c->n_tips != N) {
+            c->patterns_set = false;
+            c->bm_n = 0;  // branch models are per branch of the old tree
+        }
         c->n_tips = N;
         c->parent.assign(parent, parent + 2 * N - 1);
         build_levels(c);
@@ -760,6 +786,7 @@ int pg_set_model(pg_ctx* c, int32_t m, const double* Q, const double* pi, int32_
             ws += catw[l];
         }
         if (std::fabs(ws - 1.0) > 1e-12) return fail(c, PG_E_MODEL, "category weights do not sum to 1");
+        const int old_m = c->m;
         c->m = m;
         c->K = K;
         c->Q.assign(Q, Q + m * m);
@@ -775,7 +802,67 @@ int pg_set_model(pg_ctx* c, int32_t m, const double* Q, const double* pi, int32_
         c->catw.assign(catw, catw + K);
         c->qnorm = qnorm;
         if (c->precision == PG_SPLIT_BF16) prepare_split_model(c);
+        if (old_m != m) c->bm_n = 0;  // branch models have the old state count
         c->model_set = true;
+        c->dev_stale = true;
+        c->have_partials = false;
+        return PG_OK;
+    });
+}
+
+int pg_set_branch_models(pg_ctx* c, int32_t n_models, const double* Q, const int32_t* model_of_branch) {
+    if (!c) return PG_E_INVALID;
+    if (!c->tree_set || !c->model_set) return fail(c, PG_E_STATE, "set the tree and the model first");
+    if (n_models < 0) return fail(c, PG_E_INVALID, "n_models < 0");
+    if (n_models > 0 && (!Q || !model_of_branch)) return fail(c, PG_E_INVALID, "NULL Q or model_of_branch");
+    if (n_models > 0 && c->precision == PG_SPLIT_BF16)
+        return fail(c, PG_E_UNSUPPORTED, "per-branch rate matrices have no split-BF16 kernel");
+    return guarded(c, [&] {
+        const int m = c->m, B = 2 * c->n_tips - 2;
+        std::vector<double> Qs, Q2s, qn;
+        std::vector<int> model;
+        if (n_models > 0) {
+            Qs.assign(Q, Q + (size_t)n_models * m * m);
+            Q2s.assign(Qs.size(), 0.0);
+            qn.assign(n_models, 0.0);
+            for (int k = 0; k < n_models; ++k) {
+                const double* Qk = Qs.data() + (size_t)k * m * m;
+                double amax = 1.0;
+                for (int i = 0; i < m * m; ++i) {
+                    if (!std::isfinite(Qk[i])) return fail(c, PG_E_MODEL, "rate matrix has a non-finite entry");
+                    amax = std::max(amax, std::fabs(Qk[i]));
+                }
+                for (int x = 0; x < m; ++x) {
+                    double row = 0.0, rabs = 0.0;
+                    for (int y = 0; y < m; ++y) {
+                        if (x != y && Qk[x * m + y] < 0.0)
+                            return fail(c, PG_E_MODEL, "rate matrix " + std::to_string(k) +
+                                                           " has a negative off-diagonal rate");
+                        row += Qk[x * m + y];
+                        rabs += std::fabs(Qk[x * m + y]);
+                    }
+                    if (std::fabs(row) > 1e-12 * amax * m)
+                        return fail(c, PG_E_MODEL, "a row of rate matrix " + std::to_string(k) + " does not sum to 0");
+                    qn[k] = std::max(qn[k], rabs);
+                }
+                double* Q2k = Q2s.data() + (size_t)k * m * m;
+                for (int x = 0; x < m; ++x)
+                    for (int y = 0; y < m; ++y) {
+                        double acc = 0.0;
+                        for (int z = 0; z < m; ++z) acc += Qk[x * m + z] * Qk[z * m + y];
+                        Q2k[x * m + y] = acc;
+                    }
+            }
+            model.assign(model_of_branch, model_of_branch + B);
+            for (int b = 0; b < B; ++b)
+                if (model[b] < 0 || model[b] >= n_models)
+                    return fail(c, PG_E_INVALID, "model_of_branch[" + std::to_string(b) + "] out of range");
+        }
+        c->bm_n = n_models;
+        c->bm_Q.swap(Qs);
+        c->bm_Q2.swap(Q2s);
+        c->bm_qnorm.swap(qn);
+        c->bm_model.swap(model);
         c->dev_stale = true;
         c->have_partials = false;
         return PG_OK;

@@ -240,6 +240,15 @@ __device__ inline void lds_barrier() {
 
 constexpr int TAYLOR_DEG = 16;
 
+// Rate matrix and its norm on branch b: the model's, or the branch's own
+// in a non-homogeneous model.
+__device__ inline const double* branch_q(const EvalArgs& a, int b, int M) {
+    return a.n_models ? a.Qm + (size_t)a.branch_model[b] * M * M : a.Q64;
+}
+__device__ inline double branch_qnorm(const EvalArgs& a, int b) {
+    return a.n_models ? a.qnorm_m[a.branch_model[b]] : a.qnorm;
+}
+
 __device__ inline bool bad_length(double t) { return !(t >= 0.0) || isinf(t); }
 
 template <int M>
@@ -269,7 +278,8 @@ __device__ inline void pmat_reg_body(const EvalArgs& a, int block) {
         return;
     }
     const double h = a.rates[l] * tb;
-    double nrm = a.qnorm * h;
+    const double* Qb = branch_q(a, b, M);
+    double nrm = branch_qnorm(a, b) * h;
     int s = 0;
     while (nrm > 0.5 && s < 1100) { nrm *= 0.5; ++s; }
     const double hs = ldexp(h, -s);
@@ -278,7 +288,7 @@ __device__ inline void pmat_reg_body(const EvalArgs& a, int block) {
     for (int i = 0; i < M; ++i)
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            A[i][j] = a.Q64[i * M + j] * hs;
+            A[i][j] = Qb[i * M + j] * hs;
             G[i][j] = (i == j) ? 1.0 : 0.0;
         }
     for (int k = TAYLOR_DEG; k >= 2; --k) {
@@ -316,12 +326,13 @@ __device__ inline void pmat_lds_body(const EvalArgs& a, int block) {
         return;
     }
     const double h = a.rates[l] * tb;
-    double nrm = a.qnorm * h;
+    const double* Qb = branch_q(a, b, M);
+    double nrm = branch_qnorm(a, b) * h;
     int s = 0;
     while (nrm > 0.5 && s < 1100) { nrm *= 0.5; ++s; }
     const double hs = ldexp(h, -s);
     for (int e = threadIdx.x; e < M * M; e += blockDim.x) {
-        A[e] = a.Q64[e] * hs;
+        A[e] = Qb[e] * hs;
         G[e] = (e / M == e % M) ? 1.0 : 0.0;
     }
     __syncthreads();
@@ -529,18 +540,24 @@ __device__ inline void pre_child(const EvalArgs& a, int c, int l, int tile, int 
     T u[M];
 #pragma unroll
     for (int x = 0; x < M; ++x) u[x] = q[x] * msib[x];
+    // Q (and Q^2) of branch c: the model's, or in a non-homogeneous model
+    // the branch's own
+    const double* Qc = a.n_models ? a.Qm + (size_t)a.branch_model[c] * M * M : nullptr;
+    const double* Q2c = a.n_models ? a.Q2m + (size_t)a.branch_model[c] * M * M : nullptr;
     T den = T(0), num = T(0), num2 = T(0);
 #pragma unroll
     for (int x = 0; x < M; ++x) {
         T qm = T(0);
 #pragma unroll
-        for (int y = 0; y < M; ++y) qm = fma(T(qentry<M>(a, x * M + y)), mown[y], qm);
+        for (int y = 0; y < M; ++y)
+            qm = fma(T(Qc ? Qc[x * M + y] : qentry<M>(a, x * M + y)), mown[y], qm);
         num = fma(u[x], qm, num);
         den = fma(u[x], mown[x], den);
         if constexpr (HESS) {
             T q2m = T(0);
 #pragma unroll
-            for (int y = 0; y < M; ++y) q2m = fma(T(q2entry<M>(a, x * M + y)), mown[y], q2m);
+            for (int y = 0; y < M; ++y)
+                q2m = fma(T(Q2c ? Q2c[x * M + y] : q2entry<M>(a, x * M + y)), mown[y], q2m);
             num2 = fma(u[x], q2m, num2);
         }
     }

@@ -71,6 +71,13 @@ struct EvalArgs {
     double* logL_out;                  // [1] logL destination
     int* status;                       // [1] written by each logL reduction: 0 ok,
                                        //     1 NaN (bad length), 2 zero likelihood
+    // non-homogeneous model (n_models > 0): branch b uses rate matrix
+    // Qm[branch_model[b]] instead of Q64 / Qs
+    int n_models;
+    const int* branch_model;           // [B]
+    const double* Qm;                  // [n_models][M][M]
+    const double* Q2m;                 // [n_models][M][M] squares
+    const double* qnorm_m;             // [n_models] max row abs sum
     // split-BF16 path: states padded to MP, P holds per-(branch, category)
     // operand slots of MF_SLOT_BYTES, msg/qv hold MP x TP FP32 per tile
     const double* eV;                  // [MP][MP] V of Q = V B V^-1, identity on padding

@@ -278,10 +278,9 @@ def main():
         n_int = N - 2
         mf = {"post": 48 * n_int, "pre": 48 * (2 * N - 2) + 48 * n_int}
         fl = mf[dom] * n_tiles * 16384
-        roofline["mfma"] = {"kernel": dom, "bf16_flops_per_launch": fl,
-                            "achieved": round(fl / (avg_ms[dom] * 1e-3) / 1e12, 2), "peak": 2500.0,
-                            "unit": "TFLOP/s",
-                            "frac": round(fl / (avg_ms[dom] * 1e-3) / 1e12 / 2500.0, 4)}
+        tf = fl / (avg_ms[dom] * 1e-3) / 1e12 if avg_ms[dom] > 0 else 0.0
+        roofline["mfma"] = {"kernel": dom, "bf16_flops_per_launch": fl, "achieved": round(tf, 2),
+                            "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4)}
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "evals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),

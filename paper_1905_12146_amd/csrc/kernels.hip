@@ -534,31 +534,46 @@ __global__ void __launch_bounds__(LOGL_THREADS) logl_kernel(EvalArgs a) {
 //   tile sum of w_s rho gamma^2 (u^T Q^2 m)/(u^T m)   -> partial2[tile][c]
 //   rho gamma (u^T Q m)/(u^T m) for every pattern     -> r1[c][l][s]
 // so d2 logL/dt_c^2 = sum partial2 - sum_s w_s (sum_l r1)^2.
-template <int M, typename T, bool HESS>
+template <int M, typename T, bool HESS, bool NH>
 __device__ inline void pre_child(const EvalArgs& a, int c, int l, int tile, int s, int ps, const Coef& cf,
                                  const T q[M], const T msib[M], const T mown[M], T pc, T* lds_dst) {
     T u[M];
 #pragma unroll
     for (int x = 0; x < M; ++x) u[x] = q[x] * msib[x];
-    // Q (and Q^2) of branch c: the model's, or in a non-homogeneous model
-    // the branch's own
-    const double* Qc = a.n_models ? a.Qm + (size_t)a.branch_model[c] * M * M : nullptr;
-    const double* Q2c = a.n_models ? a.Q2m + (size_t)a.branch_model[c] * M * M : nullptr;
     T den = T(0), num = T(0), num2 = T(0);
+    if constexpr (!NH) {
+        // the model's Q (kernel arguments for small M)
 #pragma unroll
-    for (int x = 0; x < M; ++x) {
-        T qm = T(0);
+        for (int x = 0; x < M; ++x) {
+            T qm = T(0);
 #pragma unroll
-        for (int y = 0; y < M; ++y)
-            qm = fma(T(Qc ? Qc[x * M + y] : qentry<M>(a, x * M + y)), mown[y], qm);
-        num = fma(u[x], qm, num);
-        den = fma(u[x], mown[x], den);
-        if constexpr (HESS) {
-            T q2m = T(0);
+            for (int y = 0; y < M; ++y) qm = fma(T(qentry<M>(a, x * M + y)), mown[y], qm);
+            num = fma(u[x], qm, num);
+            den = fma(u[x], mown[x], den);
+            if constexpr (HESS) {
+                T q2m = T(0);
 #pragma unroll
-            for (int y = 0; y < M; ++y)
-                q2m = fma(T(Q2c ? Q2c[x * M + y] : q2entry<M>(a, x * M + y)), mown[y], q2m);
-            num2 = fma(u[x], q2m, num2);
+                for (int y = 0; y < M; ++y) q2m = fma(T(q2entry<M>(a, x * M + y)), mown[y], q2m);
+                num2 = fma(u[x], q2m, num2);
+            }
+        }
+    } else {
+        // non-homogeneous model: Q and Q^2 of branch c
+        const double* Qc = a.Qm + (size_t)a.branch_model[c] * M * M;
+        const double* Q2c = a.Q2m + (size_t)a.branch_model[c] * M * M;
+#pragma unroll
+        for (int x = 0; x < M; ++x) {
+            T qm = T(0);
+#pragma unroll
+            for (int y = 0; y < M; ++y) qm = fma(T(Qc[x * M + y]), mown[y], qm);
+            num = fma(u[x], qm, num);
+            den = fma(u[x], mown[x], den);
+            if constexpr (HESS) {
+                T q2m = T(0);
+#pragma unroll
+                for (int y = 0; y < M; ++y) q2m = fma(T(Q2c[x * M + y]), mown[y], q2m);
+                num2 = fma(u[x], q2m, num2);
+            }
         }
     }
     const double ratio = (den > T(0)) ? (double)num / (double)den : 0.0;
@@ -629,7 +644,7 @@ __device__ inline void pre_load(const EvalArgs& a, int4 nd, int l, int tile, int
 
 // top == nullptr: q of internal children goes to HBM; otherwise children in
 // the top region keep q in LDS only (it is consumed inside the region)
-template <int M, typename T, bool HESS>
+template <int M, typename T, bool HESS, bool NH>
 __device__ inline void pre_node(const EvalArgs& a, int4 nd, int l, int tile, int s, int ps, const Coef& cf,
                                 const T q[M], const PreRaw<M, T>& r, T* top) {
     T mi[M], mj[M];
@@ -644,8 +659,8 @@ __device__ inline void pre_node(const EvalArgs& a, int4 nd, int l, int tile, int
         if (const int si = rslot(nd.w, 1)) di = top_vec<M, T>(top, si, ps);
         if (const int sj = rslot(nd.w, 2)) dj = top_vec<M, T>(top, sj, ps);
     }
-    pre_child<M, T, HESS>(a, nd.y, l, tile, s, ps, cf, q, mj, mi, pi_, di);
-    pre_child<M, T, HESS>(a, nd.z, l, tile, s, ps, cf, q, mi, mj, pj_, dj);
+    pre_child<M, T, HESS, NH>(a, nd.y, l, tile, s, ps, cf, q, mj, mi, pi_, di);
+    pre_child<M, T, HESS, NH>(a, nd.z, l, tile, s, ps, cf, q, mi, mj, pj_, dj);
 }
 
 #ifndef PG_PRE_NS64
@@ -663,7 +678,9 @@ __host__ __device__ constexpr int pre_waves(int M) {
     return M * M <= TP ? (sizeof(T) == 8 ? PG_PRE_WPE64 : 4) : 1;
 }
 
-template <int M, typename T, bool HESS>
+// NH: non-homogeneous model (Q of each child's branch from a table); a
+// separate instantiation, so the homogeneous kernel keeps Q in its arguments.
+template <int M, typename T, bool HESS, bool NH>
 __device__ inline void pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
     constexpr int NS = pre_slots<T>(M);
     const int l = tile / a.n_pb, pb = tile % a.n_pb;
@@ -713,7 +730,7 @@ __device__ inline void pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
 #pragma unroll
                     for (int x = 0; x < M; ++x) q[x] = src[x * TP];
                 }
-                pre_node<M, T, HESS>(a, nd, l, tile, s, ps, cf, q, cur, top);
+                pre_node<M, T, HESS, NH>(a, nd, l, tile, s, ps, cf, q, cur, top);
             }
             if (h > a.top_level) lds_barrier();
             else __syncthreads();
@@ -739,7 +756,7 @@ __device__ inline void pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
                     nn = sched_at(a, lds_sched, nidx);
                     pre_load<M, T>(a, nn, l, tile, s, ps, nxt);
                 }
-                pre_node<M, T, HESS>(a, nd, l, tile, s, ps, cf, cur.q, cur, nullptr);
+                pre_node<M, T, HESS, NH>(a, nd, l, tile, s, ps, cf, cur.q, cur, nullptr);
                 if (!more) break;
                 nd = nn;
                 cur = nxt;
@@ -834,18 +851,18 @@ post_batch(const EvalArgs* __restrict__ reqs, const int2* __restrict__ map) {
     post_body<M, T>(reqs[m.x], m.y, lds_dyn);
 }
 
-template <int M, typename T, bool HESS>
+template <int M, typename T, bool HESS, bool NH>
 __global__ void __launch_bounds__(pre_slots<T>(M) * TP) __attribute__((amdgpu_waves_per_eu(pre_waves<T>(M))))
 pre_kernel(EvalArgs a) {
     extern __shared__ int4 lds_dyn[];
-    pre_body<M, T, HESS>(a, blockIdx.x, lds_dyn);
+    pre_body<M, T, HESS, NH>(a, blockIdx.x, lds_dyn);
 }
 template <int M, typename T>
 __global__ void __launch_bounds__(pre_slots<T>(M) * TP) __attribute__((amdgpu_waves_per_eu(pre_waves<T>(M))))
 pre_batch(const EvalArgs* __restrict__ reqs, const int2* __restrict__ map) {
     extern __shared__ int4 lds_dyn[];
     const int2 m = map[blockIdx.x];
-    pre_body<M, T, false>(reqs[m.x], m.y, lds_dyn);
+    pre_body<M, T, false, false>(reqs[m.x], m.y, lds_dyn);
 }
 
 __global__ void __launch_bounds__(GS_THREADS) gsum_kernel(EvalArgs a) { gsum_body(a, blockIdx.x); }
@@ -905,8 +922,14 @@ hipError_t launch_logl(const EvalArgs& a, hipStream_t st) {
 template <int M, typename T>
 static hipError_t pre_launch(const EvalArgs& a, hipStream_t st, bool hess) {
     const size_t lds = sched_lds_bytes(a) + top_lds_bytes(a, sizeof(T));
-    if (hess) pre_kernel<M, T, true><<<a.n_tiles, pre_slots<T>(M) * TP, lds, st>>>(a);
-    else pre_kernel<M, T, false><<<a.n_tiles, pre_slots<T>(M) * TP, lds, st>>>(a);
+    const dim3 grid(a.n_tiles), block(pre_slots<T>(M) * TP);
+    if (a.n_models) {
+        if (hess) pre_kernel<M, T, true, true><<<grid, block, lds, st>>>(a);
+        else pre_kernel<M, T, false, true><<<grid, block, lds, st>>>(a);
+    } else {
+        if (hess) pre_kernel<M, T, true, false><<<grid, block, lds, st>>>(a);
+        else pre_kernel<M, T, false, false><<<grid, block, lds, st>>>(a);
+    }
     return hipGetLastError();
 }
 

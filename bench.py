@@ -174,6 +174,41 @@ def serving_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def update_bench(args):
+    """Partial re-evaluation on the C2 workload: one logL after changing one
+    branch length (pg_logL_update: its transition matrices and the post-order
+    nodes on its path to the root), against a full logL-only evaluation
+    (pg_logL), both through the host entry points; prints one JSON line."""
+    from paper_1905_12146_amd import binding as B
+    from synth import make_workload
+
+    w = make_workload("C2")
+    prec = B.PG_FP64 if (args.precision or "fp64") == "fp64" else B.PG_FP32
+    rng = np.random.default_rng(5)
+    ctx = B.Context(0, prec)
+    ctx.set_workload(w)
+    t = w.t.copy()
+    for _ in range(5):
+        ctx.logL(t)
+    n = max(args.steps, 20)
+    t0 = time.perf_counter()
+    for _ in range(n):
+        ctx.logL(t)
+    full_us = (time.perf_counter() - t0) / n * 1e6
+    ctx.logL_update([0], [t[0]])  # switches on exponent storage (one full pass)
+    picks = rng.integers(0, len(t), size=n)
+    vals = t[picks] * np.exp(rng.normal(0.0, 0.1, size=n))
+    t0 = time.perf_counter()
+    for b, v in zip(picks, vals):
+        ctx.logL_update([int(b)], [float(v)])
+    upd_us = (time.perf_counter() - t0) / n * 1e6
+    ctx.close()
+    print(json.dumps({"metric": "single-branch logL update vs full logL (host entry points)",
+                      "workload": "C2: Yule N=1000, 4-state, K=4, S=2000", "precision": "fp64" if prec == B.PG_FP64 else "fp32",
+                      "full_logL_us": round(full_us, 1), "update_logL_us": round(upd_us, 1),
+                      "speedup": round(full_us / upd_us, 2), "calls": n}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,12 +232,17 @@ def main():
                     help="arrival rates as multiples of the one-at-a-time capacity")
     ap.add_argument("--budget-gb", type=float, default=32.0)
     ap.add_argument("--max-sessions", type=int, default=64)
+    ap.add_argument("--updates", action="store_true",
+                    help="partial re-evaluation: single-branch logL updates against full logL (C2)")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
         return
     if args.serving:
         serving_bench(args)
+        return
+    if args.updates:
+        update_bench(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "

@@ -134,6 +134,21 @@ int pg_set_model(pg_ctx* ctx, int32_t n_states, const double* Q,
  * index out of range), PG_E_MODEL, PG_E_UNSUPPORTED (PG_SPLIT_BF16). */
 int pg_set_branch_models(pg_ctx* ctx, int32_t n_models, const double* Q, const int32_t* model_of_branch);
 
+/* Partial re-evaluation: logL after changing the lengths of the n branches
+ * branches[i] to t_new[i] (i < n), the other lengths staying those of the
+ * resident partials, which must come from a host-pointer pg_logL,
+ * pg_logL_and_grad or pg_logL_update.  Recomputes only the changed
+ * transition matrices and the post-order nodes that depend on them (each
+ * changed internal node and the ancestors of every changed branch), so a
+ * single-branch change costs O(depth) nodes.  The first call on a context
+ * switches on per-node scale-exponent storage and runs one full forward
+ * pass; later full evaluations keep the exponents (2 bytes per node,
+ * pattern and category).  The result, and the partials it leaves for
+ * pg_grad, are bitwise those of a full evaluation at the new lengths.
+ * Errors: PG_E_STATE (no such partials), PG_E_INVALID, PG_E_ZERO_LIK,
+ * PG_E_UNSUPPORTED (PG_SPLIT_BF16). */
+int pg_logL_update(pg_ctx* ctx, int32_t n, const int32_t* branches, const double* t_new, double* logL);
+
 /* One evaluation from host memory: t[2N-2] branch lengths in, *logL and,
  * unless grad == NULL, grad[2N-2] = dlogL/dt_b out.  Blocks until done.
  * Errors: PG_E_STATE, PG_E_INVALID (t), PG_E_ZERO_LIK (*logL = -inf, grad

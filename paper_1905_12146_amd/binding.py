@@ -57,6 +57,7 @@ _SIGNATURES = [
     ("pg_set_branch_models", ctypes.c_int, [_vp, _i32, _vp, _vp]),
     ("pg_logL_and_grad", ctypes.c_int, [_vp, _vp, _vp, _vp]),
     ("pg_logL", ctypes.c_int, [_vp, _vp, _vp]),
+    ("pg_logL_update", ctypes.c_int, [_vp, _i32, _vp, _vp, _vp]),
     ("pg_grad", ctypes.c_int, [_vp, _vp]),
     ("pg_hessian_diag", ctypes.c_int, [_vp, _vp, _vp]),
     ("pg_logL_and_grad_device", ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -173,6 +174,17 @@ def pg_set_branch_models(ctx, Qs, model_of_branch):
     if Qs.ndim != 3 or Qs.shape[1] != Qs.shape[2] or model.ndim != 1:
         raise PhyloGradError(PG_E_INVALID, "Qs [n_models, m, m] and model_of_branch [2N-2] expected")
     _check(ctx, load().pg_set_branch_models(ctx, Qs.shape[0], _ptr(Qs), model.ctypes.data))
+
+
+def pg_logL_update(ctx, branches, t_new):
+    """logL after setting t[branches[i]] = t_new[i] (partial re-evaluation)."""
+    b = np.ascontiguousarray(branches, dtype=np.int32)
+    tn = np.ascontiguousarray(t_new, dtype=np.float64)
+    if b.shape != tn.shape or b.ndim != 1:
+        raise PhyloGradError(PG_E_INVALID, "branches and t_new must be vectors of equal length")
+    logL = ctypes.c_double()
+    _check(ctx, load().pg_logL_update(ctx, len(b), b.ctypes.data, _ptr(tn), ctypes.byref(logL)))
+    return logL.value
 
 
 def _lengths(t, n_branches):
@@ -388,6 +400,9 @@ class Context:
 
     def logL(self, t):
         return pg_logL(self.handle, t, self.n_branches)
+
+    def logL_update(self, branches, t_new):
+        return pg_logL_update(self.handle, branches, t_new)
 
     def grad(self):
         return pg_grad(self.handle, self.n_branches or 0)

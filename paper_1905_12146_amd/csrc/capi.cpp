@@ -39,6 +39,7 @@ struct pg_ctx {
     std::vector<int> parent;
     std::vector<int2> children;
     std::vector<int> level_off, level_nodes;
+    std::vector<int> height;                  // [2N-1] tips 0, cherries 1, ...
 
     // patterns
     bool patterns_set = false;
@@ -67,6 +68,14 @@ struct pg_ctx {
     // device state
     bool dev_stale = true;        // host inputs changed since the last upload
     bool have_partials = false;   // post-order pass results resident
+    // partial re-evaluation: host copy of the branch lengths of the resident
+    // partials (host-pointer evaluations only) and per-node exponents
+    std::vector<double> t_host;
+    bool t_host_valid = false;
+    bool updates = false;
+    void* u_pinned = nullptr;     // pinned staging of one update's inputs
+    size_t u_pinned_bytes = 0;
+    bool u_inflight = false;      // a copy out of u_pinned may still run
     bool device_pending = false;  // a device-pointer evaluation was enqueued
     std::map<std::string, DevBuf> bufs;
     EvalArgs args{};
@@ -238,6 +247,7 @@ void build_levels(pg_ctx* c) {
     std::vector<int> sorted(order);
     std::sort(sorted.begin(), sorted.end());
     for (int v : sorted) c->level_nodes[fill[height[v] - 1]++] = v;
+    c->height.swap(height);
 }
 
 int check_tree(pg_ctx* c, int32_t N, const int32_t* parent) {
@@ -431,6 +441,10 @@ int upload(pg_ctx* c) {
     a.logL_out = buf<double>(c, "logL");
     a.status = buf<int>(c, "status");
     a.n_models = c->bm_n;
+    if (c->updates) {
+        if ((r = ensure_buf(c, "expo", sizeof(int16_t) * (size_t)(N - 1) * n_tiles * TP))) return r;
+        a.expo = buf<int16_t>(c, "expo");
+    }
     if (c->bm_n > 0) {
         a.Qm = buf<double>(c, "bm_Q");
         a.Q2m = buf<double>(c, "bm_Q2");
@@ -646,6 +660,7 @@ void pg_destroy(pg_ctx* c) {
         (void)hipEventDestroy(p.b);
     }
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->u_pinned) (void)hipHostFree(c->u_pinned);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
 }
@@ -869,6 +884,114 @@ int pg_set_branch_models(pg_ctx* c, int32_t n_models, const double* Q, const int
     });
 }
 
+int pg_logL_update(pg_ctx* c, int32_t n, const int32_t* branches, const double* t_new, double* logL) {
+    if (!c) return PG_E_INVALID;
+    if (n < 0 || (n > 0 && (!branches || !t_new)) || !logL) return fail(c, PG_E_INVALID, "bad arguments");
+    if (c->precision == PG_SPLIT_BF16)
+        return fail(c, PG_E_UNSUPPORTED, "partial re-evaluation has no split-BF16 kernel");
+    if (!c->have_partials || c->dev_stale || !c->t_host_valid)
+        return fail(c, PG_E_STATE, "no resident partials from a host-pointer evaluation");
+    return guarded(c, [&] {
+        const int N = c->n_tips, B = 2 * N - 2;
+        for (int i = 0; i < n; ++i) {
+            if (branches[i] < 0 || branches[i] >= B)
+                return fail(c, PG_E_INVALID, "branch index " + std::to_string(branches[i]) + " out of range");
+            if (!std::isfinite(t_new[i]) || t_new[i] < 0.0)
+                return fail(c, PG_E_INVALID, "new length of branch " + std::to_string(branches[i]) +
+                                                 " is not finite and >= 0");
+        }
+        PG_HIP(c, hipSetDevice(c->device));
+        std::vector<double> t = c->t_host;
+        for (int i = 0; i < n; ++i) t[branches[i]] = t_new[i];
+        int r;
+        if (!c->updates) {
+            // first update: keep per-node exponents from now on, by one
+            // full evaluation at the new lengths
+            c->updates = true;
+            c->dev_stale = true;
+            if ((r = upload(c))) return r;
+            c->have_partials = false;
+            c->t_host_valid = false;
+            PG_HIP(c, hipMemcpyAsync((void*)c->args.t, t.data(), sizeof(double) * B, hipMemcpyHostToDevice,
+                                     c->stream));
+            if ((r = enqueue_forward(c, c->args, true))) return r;
+        } else {
+            // dirty nodes: each changed internal node (its message changes
+            // with its matrix) and every ancestor of a changed branch
+            std::vector<char> dirty(2 * N - 1, 0);
+            std::vector<int> list;
+            for (int i = 0; i < n; ++i) {
+                const int b = branches[i];
+                if (std::find(list.begin(), list.end(), b) == list.end()) list.push_back(b);
+                for (int v = (b >= N) ? b : c->parent[b]; v >= 0 && !dirty[v]; v = c->parent[v]) dirty[v] = 1;
+            }
+            const int H = (int)c->level_off.size() - 1;
+            std::vector<int> off(H + 1, 0);
+            std::vector<int4> sched;
+            for (int h = 0; h < H; ++h) {
+                for (int i = c->level_off[h]; i < c->level_off[h + 1]; ++i) {
+                    const int k = c->level_nodes[i];
+                    if (dirty[k]) sched.push_back(make_int4(k, c->children[k].x, c->children[k].y, 0));
+                }
+                off[h + 1] = (int)sched.size();
+            }
+            // one pinned staging area and one copy: [t][branch list][schedule][level offsets]
+            const size_t o_list = sizeof(double) * B;
+            const size_t o_sched = (o_list + sizeof(int) * B + 15) & ~size_t(15);
+            const size_t o_level = o_sched + sizeof(int4) * (N - 1);
+            const size_t bytes = o_level + sizeof(int) * (H + 1);
+            if (c->u_pinned_bytes < bytes) {
+                if (c->u_pinned) (void)hipHostFree(c->u_pinned);
+                c->u_pinned = nullptr;
+                c->u_pinned_bytes = 0;
+                PG_HIP(c, hipStreamSynchronize(c->stream));
+                PG_HIP(c, hipHostMalloc(&c->u_pinned, bytes));
+                c->u_pinned_bytes = bytes;
+            }
+            if ((r = ensure_buf(c, "u_stage", bytes))) return r;
+            // a successful call ends with finish_host, which waits for the
+            // stream; after an error, wait here before reusing the staging area
+            if (c->u_inflight) PG_HIP(c, hipStreamSynchronize(c->stream));
+            c->u_inflight = false;
+            char* hs = static_cast<char*>(c->u_pinned);
+            std::memcpy(hs, t.data(), sizeof(double) * B);
+            std::memcpy(hs + o_list, list.data(), sizeof(int) * list.size());
+            std::memcpy(hs + o_sched, sched.data(), sizeof(int4) * sched.size());
+            std::memcpy(hs + o_level, off.data(), sizeof(int) * off.size());
+            char* ds = static_cast<char*>(c->bufs["u_stage"].ptr);
+            c->have_partials = false;
+            c->t_host_valid = false;
+            hipStream_t st = c->stream;
+            c->u_inflight = true;
+            PG_HIP(c, hipMemcpyAsync(ds, hs, bytes, hipMemcpyHostToDevice, st));
+            PG_HIP(c, hipMemcpyAsync((void*)c->args.t, ds, sizeof(double) * B, hipMemcpyDeviceToDevice, st));
+            EvalArgs a = c->args;
+            if (!list.empty()) {
+                a.blist = reinterpret_cast<const int*>(ds + o_list);
+                a.n_blist = (int)list.size();
+                if ((r = timed(c, PG_K_PMAT, [&] { return launch_pmat(a, c->precision, st); }))) return r;
+            }
+            EvalArgs p = c->args;
+            p.sched = reinterpret_cast<const int4*>(ds + o_sched);
+            p.sched_lds = 0;
+            p.level_off = reinterpret_cast<const int*>(ds + o_level);
+            p.top_level = p.n_levels;
+            p.expo_delta = 1;
+            if ((r = timed(c, PG_K_POST, [&] { return launch_post(p, c->precision, st); }))) return r;
+            if ((r = timed(c, PG_K_ROOT, [&] { return launch_logl(c->args, st); }))) return r;
+        }
+        r = finish_host(c, logL, nullptr);
+        if (r != PG_E_DEVICE) c->u_inflight = false;
+        if (r == PG_E_ZERO_LIK) *logL = -INFINITY;
+        if (r == PG_OK) {
+            c->have_partials = true;
+            c->t_host = t;
+            c->t_host_valid = true;
+        }
+        return r;
+    });
+}
+
 int pg_logL(pg_ctx* c, const double* t, double* logL) {
     if (!c) return PG_E_INVALID;
     if (!t || !logL) return fail(c, PG_E_INVALID, "NULL t or logL");
@@ -878,12 +1001,17 @@ int pg_logL(pg_ctx* c, const double* t, double* logL) {
         if ((r = check_lengths(c, t))) return r;
         PG_HIP(c, hipSetDevice(c->device));
         c->have_partials = false;
+        c->t_host_valid = false;
         PG_HIP(c, hipMemcpyAsync((void*)c->args.t, t, sizeof(double) * c->args.n_branches,
                                  hipMemcpyHostToDevice, c->stream));
         if ((r = enqueue_forward(c, c->args, true))) return r;
         r = finish_host(c, logL, nullptr);
         if (r == PG_E_ZERO_LIK) *logL = -INFINITY;
-        if (r == PG_OK) c->have_partials = true;
+        if (r == PG_OK) {
+            c->have_partials = true;
+            c->t_host.assign(t, t + c->args.n_branches);
+            c->t_host_valid = true;
+        }
         return r;
     });
 }
@@ -912,13 +1040,18 @@ int pg_logL_and_grad(pg_ctx* c, const double* t, double* logL, double* grad) {
         if ((r = check_lengths(c, t))) return r;
         PG_HIP(c, hipSetDevice(c->device));
         c->have_partials = false;
+        c->t_host_valid = false;
         PG_HIP(c, hipMemcpyAsync((void*)c->args.t, t, sizeof(double) * c->args.n_branches,
                                  hipMemcpyHostToDevice, c->stream));
         if ((r = enqueue_forward(c, c->args, false))) return r;
         if ((r = enqueue_backward(c, c->args))) return r;
         r = finish_host(c, logL, grad);
         if (r == PG_E_ZERO_LIK) *logL = -INFINITY;
-        if (r == PG_OK) c->have_partials = true;
+        if (r == PG_OK) {
+            c->have_partials = true;
+            c->t_host.assign(t, t + c->args.n_branches);
+            c->t_host_valid = true;
+        }
         return r;
     });
 }
@@ -953,6 +1086,7 @@ int pg_logL_and_grad_device(pg_ctx* c, const double* d_t, double* d_logL, double
         int r = upload(c);
         if (r) return r;
         PG_HIP(c, hipSetDevice(c->device));
+        c->t_host_valid = false;  // lengths of the resident partials are on the device only
         EvalArgs a = c->args;
         a.t = d_t;
         a.logL_out = d_logL;

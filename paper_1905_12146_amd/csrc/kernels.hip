@@ -268,8 +268,8 @@ __device__ inline void matmul_reg(const double A[M][M], const double B[M][M], do
 template <int M, typename T>
 __device__ inline void pmat_reg_body(const EvalArgs& a, int block) {
     const int idx = block * 256 + threadIdx.x;
-    if (idx >= a.n_branches * a.K) return;
-    const int b = idx / a.K, l = idx % a.K;
+    if (idx >= (a.blist ? a.n_blist : a.n_branches) * a.K) return;
+    const int b = a.blist ? a.blist[idx / a.K] : idx / a.K, l = idx % a.K;
     const double tb = a.t[b];
     T* out = static_cast<T*>(a.P) + ((size_t)b * a.K + l) * M * M;
     if (bad_length(tb)) {
@@ -318,7 +318,7 @@ template <int M, typename T>
 __device__ inline void pmat_lds_body(const EvalArgs& a, int block) {
     __shared__ double A[M * M], G[M * M], W[M * M];
     const int idx = block;
-    const int b = idx / a.K, l = idx % a.K;
+    const int b = a.blist ? a.blist[idx / a.K] : idx / a.K, l = idx % a.K;
     const double tb = a.t[b];
     T* out = static_cast<T*>(a.P) + ((size_t)b * a.K + l) * M * M;
     if (bad_length(tb)) {
@@ -398,8 +398,17 @@ __device__ inline void post_node(const EvalArgs& a, int4 nd, int l, int tile, in
 #pragma unroll
         for (int x = 0; x < M; ++x) p[x] = pow2_scale(p[x], -e);
     }
-    esum += e;
     const int k = nd.x;
+    if (a.expo) {
+        // per-node exponents for partial re-evaluation: a pass over some
+        // nodes adds the change of each visited node's exponent
+        int16_t* ex = a.expo + ((size_t)(k - a.n_tips) * a.n_tiles + tile) * TP + ps;
+        if (a.expo_delta) esum += e - (int)*ex;
+        else esum += e;
+        *ex = (int16_t)e;
+    } else {
+        esum += e;
+    }
     if (k != a.root) {
         T mk[M];
         if constexpr (RowMat<M>::value) {
@@ -476,7 +485,8 @@ __device__ inline void post_body(const EvalArgs& a, int tile, int4* lds_sched) {
     if (ns == 0) {
         int tot = 0;
         for (int i = 0; i < NS; ++i) tot += red[i][ps];
-        a.rootE[(size_t)l * a.S_pad + s] = tot;
+        if (a.expo_delta) a.rootE[(size_t)l * a.S_pad + s] += tot;
+        else a.rootE[(size_t)l * a.S_pad + s] = tot;
     }
 }
 
@@ -880,12 +890,9 @@ bool kernel_supported(int M, int precision) {
 
 template <int M, typename T>
 static hipError_t pmat_launch(const EvalArgs& a, hipStream_t st) {
-    if constexpr (M <= 8) {
-        const int n = a.n_branches * a.K;
-        pmat_reg_kernel<M, T><<<(n + 255) / 256, 256, 0, st>>>(a);
-    } else {
-        pmat_lds_kernel<M, T><<<a.n_branches * a.K, 256, 0, st>>>(a);
-    }
+    const int n = (a.blist ? a.n_blist : a.n_branches) * a.K;
+    if constexpr (M <= 8) pmat_reg_kernel<M, T><<<(n + 255) / 256, 256, 0, st>>>(a);
+    else pmat_lds_kernel<M, T><<<n, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -78,6 +78,13 @@ struct EvalArgs {
     const double* Qm;                  // [n_models][M][M]
     const double* Q2m;                 // [n_models][M][M] squares
     const double* qnorm_m;             // [n_models] max row abs sum
+    // partial re-evaluation: pmat over a branch list, per-node scale
+    // exponents kept so a post-order pass over some nodes can patch rootE
+    const int* blist;                  // [n_blist] branches whose P to form (NULL: all)
+    int n_blist;
+    int16_t* expo;                     // [N-1][n_tiles][TP] exponent of each node (NULL: off)
+    int expo_delta;                    // 1: this post-order pass visits only some nodes;
+                                       //    rootE += sum of (new - stored) exponents
     // split-BF16 path: states padded to MP, P holds per-(branch, category)
     // operand slots of MF_SLOT_BYTES, msg/qv hold MP x TP FP32 per tile
     const double* eV;                  // [MP][MP] V of Q = V B V^-1, identity on padding

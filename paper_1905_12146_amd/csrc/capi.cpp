@@ -244,10 +244,149 @@ void build_levels(pg_ctx* c) {
     for (int h = 1; h <= H; ++h) c->level_off[h] = c->level_off[h - 1] + count[h];
     c->level_nodes.assign(N - 1, 0);
     std::vector<int> fill(c->level_off.begin(), c->level_off.end() - 1);
+    // within a level: nodes with two internal children, then one, then none,
+    // each group by label.  Consecutive node slots share a wavefront, so the
+    // grouping keeps the tip and internal child paths of the kernels from
+    // both running in one wavefront for most of the level.
     std::vector<int> sorted(order);
-    std::sort(sorted.begin(), sorted.end());
+    auto n_tip_children = [&](int v) { return (c->children[v].x < N) + (c->children[v].y < N); };
+    std::sort(sorted.begin(), sorted.end(), [&](int u, int v) {
+        const int cu = n_tip_children(u), cv = n_tip_children(v);
+        return cu != cv ? cu < cv : u < v;
+    });
     for (int v : sorted) c->level_nodes[fill[height[v] - 1]++] = v;
     c->height.swap(height);
+}
+
+// Traversal schedule of one upload: the level-synchronous part (the top:
+// every internal node outside the clades, grouped by height within the top)
+// and the clade walks, one list per slot count.
+struct Schedule {
+    std::vector<int> level_off;       // [H + 1] top levels
+    std::vector<int> level_nodes;     // top nodes by level
+    std::vector<int4> cl_post, cl_pre;
+    std::vector<int> cl_post_off, cl_pre_off;
+    int depth = 0;                    // stack blocks per slot
+};
+
+// LPT assignment of clades to ns slots (largest clade to the least loaded
+// slot); entries slot-major.
+void assign_clades(const std::vector<std::vector<int4>>& clades, int ns, std::vector<int4>& out,
+                   std::vector<int>& off) {
+    std::vector<int> order(clades.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int u, int v) { return clades[u].size() > clades[v].size(); });
+    std::vector<size_t> load(ns, 0);
+    std::vector<std::vector<int>> bins(ns);
+    for (int ci : order) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[b] += clades[ci].size();
+        bins[b].push_back(ci);
+    }
+    out.clear();
+    off.assign(ns + 1, 0);
+    for (int b = 0; b < ns; ++b) {
+        for (int ci : bins[b]) out.insert(out.end(), clades[ci].begin(), clades[ci].end());
+        off[b + 1] = (int)out.size();
+    }
+}
+
+// cap = 0: no clades (every internal node in the levels).
+void build_schedule(const pg_ctx* c, int cap, int ns_post, int ns_pre, Schedule& sc) {
+    const int N = c->n_tips, n_nodes = 2 * N - 1, root = n_nodes - 1;
+    const auto& ch = c->children;
+    // internal nodes in increasing height: children before parents
+    const std::vector<int>& up = c->level_nodes;
+    std::vector<int> sz(n_nodes, 0);  // internal nodes in the subtree
+    for (int v : up) sz[v] = 1 + sz[ch[v].x] + sz[ch[v].y];
+    // clade of each internal node (its clade root), -1 for the top
+    std::vector<int> clade(n_nodes, -1);
+    std::vector<int> roots;
+    for (auto it = up.rbegin(); it != up.rend(); ++it) {
+        const int v = *it;
+        if (v == root) continue;
+        const int p = c->parent[v];
+        if (clade[p] >= 0) {
+            clade[v] = clade[p];
+        } else if (sz[v] <= cap) {
+            clade[v] = v;
+            roots.push_back(v);
+        }
+    }
+    // top levels: height counted over top nodes only
+    std::vector<int> th(n_nodes, 0);
+    int H = 0;
+    for (int v : up) {
+        if (clade[v] >= 0) continue;
+        int h = 0;
+        for (int cc : {ch[v].x, ch[v].y})
+            if (cc >= N && clade[cc] < 0) h = std::max(h, th[cc]);
+        th[v] = h + 1;
+        H = std::max(H, th[v]);
+    }
+    std::vector<int> count(H + 1, 0), top;
+    for (int v : up)
+        if (clade[v] < 0) {
+            count[th[v]]++;
+            top.push_back(v);
+        }
+    sc.level_off.assign(H + 1, 0);
+    for (int h = 1; h <= H; ++h) sc.level_off[h] = sc.level_off[h - 1] + count[h];
+    // within a level: nodes with two internal children, then one, then none,
+    // each group by label.  Consecutive node slots share a wavefront, so the
+    // grouping keeps the tip and internal child paths of the kernels from
+    // both running in one wavefront for most of the level.
+    auto n_tip_children = [&](int v) { return (ch[v].x < N) + (ch[v].y < N); };
+    std::sort(top.begin(), top.end(), [&](int u, int v) {
+        const int cu = n_tip_children(u), cv = n_tip_children(v);
+        return cu != cv ? cu < cv : u < v;
+    });
+    sc.level_nodes.assign(top.size(), 0);
+    std::vector<int> fill(sc.level_off.begin(), sc.level_off.end() - 1);
+    for (int v : top) sc.level_nodes[fill[th[v] - 1]++] = v;
+    // clade entries in post order, the child with more internal nodes first
+    auto ordered = [&](int v) {
+        int f = ch[v].x, g = ch[v].y;
+        if (sz[g] > sz[f]) std::swap(f, g);
+        return std::make_pair(f, g);
+    };
+    std::sort(roots.begin(), roots.end());
+    std::vector<std::vector<int4>> lists;
+    sc.depth = 0;
+    for (int r : roots) {
+        std::vector<int4> e;
+        std::vector<std::pair<int, bool>> st{{r, false}};
+        while (!st.empty()) {
+            const auto [v, done] = st.back();
+            st.pop_back();
+            const auto [f, g] = ordered(v);
+            if (done) {
+                int flags = 0;
+                if (v == r) {
+                    flags = CL_ROOT;
+                } else {
+                    const auto [pf, pg2] = ordered(c->parent[v]);
+                    if (v == pf && pg2 >= N) flags = CL_STACK;
+                }
+                e.push_back(make_int4(v, f, g, flags));
+                continue;
+            }
+            st.push_back({v, true});
+            if (g >= N) st.push_back({g, false});
+            if (f >= N) st.push_back({f, false});
+        }
+        // stack depth of the walk (pops before pushes within an entry)
+        int sp = 0;
+        for (const int4& x : e) {
+            if (x.y >= N && x.z >= N) --sp;
+            if (x.w & CL_STACK) ++sp;
+            sc.depth = std::max(sc.depth, sp);
+        }
+        lists.push_back(std::move(e));
+    }
+    assign_clades(lists, ns_post, sc.cl_post, sc.cl_post_off);
+    assign_clades(lists, ns_pre, sc.cl_pre, sc.cl_pre_off);
 }
 
 int check_tree(pg_ctx* c, int32_t N, const int32_t* parent) {
@@ -317,8 +456,24 @@ int upload(pg_ctx* c) {
     if ((r = ensure_buf(c, "qv", es * vec * (N - 1)))) return r;
     if ((r = ensure_buf(c, "codes", (size_t)N * c->S_pad))) return r;
     if ((r = ensure_buf(c, "masks", sizeof(unsigned long long) * 256))) return r;
-    if ((r = ensure_buf(c, "level_off", sizeof(int) * c->level_off.size()))) return r;
-    if ((r = ensure_buf(c, "sched", sizeof(int4) * c->level_nodes.size()))) return r;
+    // traversal schedule: clades for the small-M FP64 / FP32 kernels, with a
+    // smaller cap when a deep clade's stack would not fit CLADE_STACK_MAX
+    const int ns_post = node_slots(M), ns_pre = split ? ns_post : pre_node_slots(M, c->precision);
+    Schedule sc;
+    {
+        int cap = (!split && M * M <= TP) ? CLADE_CAP : 0;
+        build_schedule(c, cap, ns_post, ns_pre, sc);
+        while (cap > 0 && es * std::max(ns_post, ns_pre) * sc.depth * M * TP > (size_t)CLADE_STACK_MAX) {
+            cap = cap * 3 / 4;
+            build_schedule(c, cap, ns_post, ns_pre, sc);
+        }
+    }
+    const int n_top = (int)sc.level_nodes.size(), n_cl = (int)sc.cl_post.size();
+    const bool one_list = ns_post == ns_pre;
+    const size_t n_entries = (size_t)n_top + n_cl * (one_list ? 1 : 2);
+    if ((r = ensure_buf(c, "level_off", sizeof(int) * sc.level_off.size()))) return r;
+    if ((r = ensure_buf(c, "sched", sizeof(int4) * n_entries))) return r;
+    if ((r = ensure_buf(c, "cl_off", sizeof(int) * (ns_post + ns_pre + 2)))) return r;
     if ((r = ensure_buf(c, "Q64", sizeof(double) * M * M))) return r;
     if ((r = ensure_buf(c, "Q2_64", sizeof(double) * M * M))) return r;
     if ((r = ensure_buf(c, "pi64", sizeof(double) * M))) return r;
@@ -348,11 +503,11 @@ int upload(pg_ctx* c) {
     };
     // pre-order top region: levels from the root down while every level has
     // at most TOP_LEVEL_MAX_NODES nodes and their q vectors fit TOP_LDS_MAX
-    const int H = (int)c->level_off.size() - 1;
+    const int H = (int)sc.level_off.size() - 1;
     const int top_cap = std::min<int>(255, TOP_LDS_MAX / (int)(es * M * TP));
     int top_level = H, top_nodes = 0;
     for (int h = H - 1; h >= 0 && !split; --h) {
-        const int n_h = c->level_off[h + 1] - c->level_off[h];
+        const int n_h = sc.level_off[h + 1] - sc.level_off[h];
         if (n_h > TOP_LEVEL_MAX_NODES || top_nodes + n_h > top_cap) break;
         top_nodes += n_h;
         top_level = h;
@@ -360,18 +515,27 @@ int upload(pg_ctx* c) {
     std::vector<int> region(n_nodes, 0);
     {
         int next = 1;
-        for (int i = c->level_off[top_level]; i < c->level_off[H]; ++i) region[c->level_nodes[i]] = next++;
+        for (int i = sc.level_off[top_level]; i < sc.level_off[H]; ++i) region[sc.level_nodes[i]] = next++;
     }
-    std::vector<int4> sched(c->level_nodes.size());
-    for (size_t i = 0; i < sched.size(); ++i) {
-        const int k = c->level_nodes[i];
-        const int c0 = c->children[k].x, c1 = c->children[k].y;
+    // [top entries][post clade list][pre clade list unless the same]
+    std::vector<int4> sched(n_entries);
+    for (int i = 0; i < n_top; ++i) {
+        const int k = sc.level_nodes[i];
+        // a node with one tip child lists its internal child first, so the
+        // first child of every such node takes the same path
+        int c0 = c->children[k].x, c1 = c->children[k].y;
+        if (c0 < N && c1 >= N) std::swap(c0, c1);
         sched[i] = make_int4(k, c0, c1, region[k] | (region[c0] << 8) | (region[c1] << 16));
     }
+    std::copy(sc.cl_post.begin(), sc.cl_post.end(), sched.begin() + n_top);
+    if (!one_list) std::copy(sc.cl_pre.begin(), sc.cl_pre.end(), sched.begin() + n_top + n_cl);
+    std::vector<int> cl_off(sc.cl_post_off);
+    cl_off.insert(cl_off.end(), sc.cl_pre_off.begin(), sc.cl_pre_off.end());
     PG_HIP(c, put("codes", c->codes.data(), c->codes.size()));
     PG_HIP(c, put("masks", c->masks.data(), sizeof(unsigned long long) * 256));
-    PG_HIP(c, put("level_off", c->level_off.data(), sizeof(int) * c->level_off.size()));
+    PG_HIP(c, put("level_off", sc.level_off.data(), sizeof(int) * sc.level_off.size()));
     PG_HIP(c, put("sched", sched.data(), sizeof(int4) * sched.size()));
+    PG_HIP(c, put("cl_off", cl_off.data(), sizeof(int) * cl_off.size()));
     PG_HIP(c, put("Q64", c->Q.data(), sizeof(double) * M * M));
     PG_HIP(c, put("Q2_64", c->Q2.data(), sizeof(double) * M * M));
     PG_HIP(c, put("pi64", c->pi.data(), sizeof(double) * M));
@@ -407,7 +571,7 @@ int upload(pg_ctx* c) {
     a.S_pad = c->S_pad;
     a.n_pb = n_pb;
     a.n_tiles = n_tiles;
-    a.n_levels = (int)c->level_off.size() - 1;
+    a.n_levels = H;
     a.qnorm = c->qnorm;
     for (int e = 0; e < 16; ++e) a.Qs[e] = (e < M * M) ? c->Q[e] : 0.0;
     for (int e = 0; e < 16; ++e) a.Q2s[e] = (e < M * M) ? c->Q2[e] : 0.0;
@@ -420,9 +584,23 @@ int upload(pg_ctx* c) {
     a.masks = buf<unsigned long long>(c, "masks");
     a.level_off = buf<int>(c, "level_off");
     a.sched = buf<int4>(c, "sched");
-    a.sched_lds = (sizeof(int4) * (size_t)(N - 1) <= (size_t)SCHED_LDS_MAX) ? 1 : 0;
     a.top_level = top_level;
     a.top_nodes = top_nodes;
+    a.n_sched = n_top;
+    if (n_cl > 0) {
+        a.n_cl = n_cl;
+        a.cl_depth = sc.depth;
+        a.cl_post = a.sched + n_top;
+        a.cl_pre = one_list ? a.cl_post : a.cl_post + n_cl;
+        a.cl_post_off = buf<int>(c, "cl_off");
+        a.cl_pre_off = a.cl_post_off + ns_post + 1;
+    }
+    // stage the schedule in LDS when it fits and leaves each kernel's total
+    // within LDS_BLOCK_MAX
+    a.sched_lds = (sizeof(int4) * (size_t)(n_top + n_cl) <= (size_t)SCHED_LDS_MAX) ? 1 : 0;
+    if (!split && (post_lds_bytes(a, c->precision) > (size_t)LDS_BLOCK_MAX ||
+                   pre_lds_bytes(a, c->precision) > (size_t)LDS_BLOCK_MAX))
+        a.sched_lds = 0;
     a.Q64 = buf<double>(c, "Q64");
     a.Q2_64 = buf<double>(c, "Q2_64");
     a.pi64 = buf<double>(c, "pi64");
@@ -975,6 +1153,9 @@ int pg_logL_update(pg_ctx* c, int32_t n, const int32_t* branches, const double* 
             p.sched = reinterpret_cast<const int4*>(ds + o_sched);
             p.sched_lds = 0;
             p.level_off = reinterpret_cast<const int*>(ds + o_level);
+            p.n_levels = H;
+            p.n_sched = (int)sched.size();
+            p.n_cl = 0;
             p.top_level = p.n_levels;
             p.expo_delta = 1;
             if ((r = timed(c, PG_K_POST, [&] { return launch_post(p, c->precision, st); }))) return r;

@@ -210,7 +210,7 @@ __device__ inline int rslot(int w, int which) { return (w >> (8 * which)) & 0xff
 
 template <typename T>
 __device__ inline T* top_buffer(const EvalArgs& a, int4* lds_sched) {
-    return reinterpret_cast<T*>(lds_sched + (a.sched_lds ? a.n_tips - 1 : 0));
+    return reinterpret_cast<T*>(lds_sched + (a.sched_lds ? a.n_sched + a.n_cl : 0));
 }
 
 template <int M, typename T>
@@ -380,12 +380,11 @@ __device__ inline void pmat_lds_body(const EvalArgs& a, int block) {
 //   pi^T p~_root                                 Eq. (rootInnerProduct)
 // and the summed exponents of the pattern's column.
 
+// p~_k of node k from its children's messages, with the exponent
+// bookkeeping (esum, and the stored per-node exponents when kept).
 template <int M, typename T>
-__device__ inline void post_node(const EvalArgs& a, int4 nd, int l, int tile, int s, int ps,
-                                 const ChildRaw<M, T>& ri, const ChildRaw<M, T>& rj, T pk, int& esum) {
-    T mi[M], mj[M], p[M];
-    child_finish<M, T>(a, nd.y, l, ri, mi);
-    child_finish<M, T>(a, nd.z, l, rj, mj);
+__device__ inline void post_combine(const EvalArgs& a, int k, int tile, int ps, const T mi[M], const T mj[M],
+                                    T p[M], int& esum) {
     T mx = T(0);
 #pragma unroll
     for (int x = 0; x < M; ++x) {
@@ -398,7 +397,6 @@ __device__ inline void post_node(const EvalArgs& a, int4 nd, int l, int tile, in
 #pragma unroll
         for (int x = 0; x < M; ++x) p[x] = pow2_scale(p[x], -e);
     }
-    const int k = nd.x;
     if (a.expo) {
         // per-node exponents for partial re-evaluation: a pass over some
         // nodes adds the change of each visited node's exponent
@@ -409,6 +407,16 @@ __device__ inline void post_node(const EvalArgs& a, int4 nd, int l, int tile, in
     } else {
         esum += e;
     }
+}
+
+template <int M, typename T>
+__device__ inline void post_node(const EvalArgs& a, int4 nd, int l, int tile, int s, int ps,
+                                 const ChildRaw<M, T>& ri, const ChildRaw<M, T>& rj, T pk, int& esum) {
+    T mi[M], mj[M], p[M];
+    child_finish<M, T>(a, nd.y, l, ri, mi);
+    child_finish<M, T>(a, nd.z, l, rj, mj);
+    const int k = nd.x;
+    post_combine<M, T>(a, k, tile, ps, mi, mj, p, esum);
     if (k != a.root) {
         T mk[M];
         if constexpr (RowMat<M>::value) {
@@ -434,14 +442,120 @@ __device__ inline void post_node(const EvalArgs& a, int4 nd, int l, int tile, in
     }
 }
 
+// ---------------------------------------------------------------- clade walks
+//
+// Below the top of the tree each node slot walks whole clades depth first,
+// with no workgroup barrier: entries come in post order (the child with more
+// internal nodes first), so the message of the last finished node is the
+// second child's and stays in registers, and a first child whose sibling is
+// internal parks its message on the slot's LDS stack (at most log2 of the
+// clade size deep).  The pre-order walk takes the same entries backwards and
+// passes q the same way.  Row-uniform control flow throughout: a slot's 16
+// lanes always agree on the entry.
+
+template <int M, typename T>
+__device__ inline T* clade_stack(const EvalArgs& a, T* base, int ns, int ps) {
+    return base + (size_t)ns * a.cl_depth * (M * TP) + ps;
+}
+
+template <int M, typename T>
+__device__ inline void stack_push(T* stk, int& sp, const T v[M]) {
+#pragma unroll
+    for (int x = 0; x < M; ++x) stk[(sp * M + x) * TP] = v[x];
+    ++sp;
+}
+template <int M, typename T>
+__device__ inline void stack_pop(T* stk, int& sp, T v[M]) {
+    --sp;
+#pragma unroll
+    for (int x = 0; x < M; ++x) v[x] = stk[(sp * M + x) * TP];
+}
+
+// Loads of one post-order clade entry: tip children and the node's own
+// matrix entry (internal children's messages are in registers or LDS).
+template <int M, typename T>
+struct PostCladeRaw {
+    ChildRaw<M, T> r0, r1;
+    T pk;
+};
+
+template <int M, typename T>
+__device__ inline void post_clade_load(const EvalArgs& a, int4 nd, int l, int tile, int s, int ps,
+                                       PostCladeRaw<M, T>& r) {
+    if (nd.y < a.n_tips) child_load<M, T>(a, nd.y, l, tile, s, ps, r.r0);
+    if (nd.z < a.n_tips) child_load<M, T>(a, nd.z, l, tile, s, ps, r.r1);
+    r.pk = load_row_entry<M, T>(pmat_of<M, T>(a, nd.x, l), ps);
+}
+
+template <int M, typename T>
+__device__ inline void post_clades(const EvalArgs& a, const int4* lds, int l, int tile, int s, int ps, int ns,
+                                   T* stk, int& esum) {
+    static_assert(RowMat<M>::value, "clade walks use row-distributed matrices");
+    const int beg = a.cl_post_off[ns], end = a.cl_post_off[ns + 1];
+    if (beg >= end) return;
+    int sp = 0;
+    T acc[M];
+#pragma unroll
+    for (int x = 0; x < M; ++x) acc[x] = T(0);
+    int4 nd = clade_at(a, lds, a.cl_post, beg);
+    PostCladeRaw<M, T> cur;
+    post_clade_load<M, T>(a, nd, l, tile, s, ps, cur);
+    for (int i = beg;; ++i) {
+        const bool more = i + 1 < end;
+        int4 nn = nd;
+        PostCladeRaw<M, T> nxt;
+        if (more) {
+            nn = clade_at(a, lds, a.cl_post, i + 1);
+            post_clade_load<M, T>(a, nn, l, tile, s, ps, nxt);
+        }
+        T m0[M], m1[M], p[M], mk[M];
+        if (nd.y < a.n_tips) {
+            child_finish<M, T>(a, nd.y, l, cur.r0, m0);
+        } else if (nd.z < a.n_tips) {
+#pragma unroll
+            for (int x = 0; x < M; ++x) m0[x] = acc[x];
+        } else {
+            stack_pop<M, T>(stk, sp, m0);
+        }
+        if (nd.z < a.n_tips) {
+            child_finish<M, T>(a, nd.z, l, cur.r1, m1);
+        } else {
+#pragma unroll
+            for (int x = 0; x < M; ++x) m1[x] = acc[x];
+        }
+        post_combine<M, T>(a, nd.x, tile, ps, m0, m1, p, esum);
+        row_matvec<M, T>(cur.pk, p, mk);
+        T* out = static_cast<T*>(a.msg) + vec_off(a, nd.x, tile, M) + ps;
+#pragma unroll
+        for (int x = 0; x < M; ++x) out[x * TP] = mk[x];
+        if (nd.w & CL_STACK) {
+            stack_push<M, T>(stk, sp, mk);
+        } else {
+#pragma unroll
+            for (int x = 0; x < M; ++x) acc[x] = mk[x];
+        }
+        if (!more) break;
+        nd = nn;
+        cur = nxt;
+    }
+}
+
 template <int M, typename T>
 __device__ inline void post_body(const EvalArgs& a, int tile, int4* lds_sched) {
     constexpr int NS = node_slots(M);
     const int l = tile / a.n_pb, pb = tile % a.n_pb;
     const int ps = threadIdx.x % TP, ns = threadIdx.x / TP;
     const int s = pb * TP + ps;
-    stage_schedule(a, lds_sched);
+    stage_schedule(a, lds_sched, a.n_cl ? a.cl_post : nullptr);
     int esum = 0;
+    if constexpr (RowMat<M>::value) {
+        // clades first: the top's lowest level reads the clade roots' messages
+        if (a.n_cl) {
+            post_clades<M, T>(a, lds_sched, l, tile, s, ps, ns,
+                              clade_stack<M, T>(a, top_buffer<T>(a, lds_sched), ns, ps), esum);
+            __syncthreads();
+        }
+    }
     for (int h = 0; h < a.n_levels; ++h) {
         const int end = a.level_off[h + 1];
         int idx = a.level_off[h] + ns;
@@ -544,9 +658,10 @@ __global__ void __launch_bounds__(LOGL_THREADS) logl_kernel(EvalArgs a) {
 //   tile sum of w_s rho gamma^2 (u^T Q^2 m)/(u^T m)   -> partial2[tile][c]
 //   rho gamma (u^T Q m)/(u^T m) for every pattern     -> r1[c][l][s]
 // so d2 logL/dt_c^2 = sum partial2 - sum_s w_s (sum_l r1)^2.
+// Returns true (and q~_c in qout) when c is internal.
 template <int M, typename T, bool HESS, bool NH>
-__device__ inline void pre_child(const EvalArgs& a, int c, int l, int tile, int s, int ps, const Coef& cf,
-                                 const T q[M], const T msib[M], const T mown[M], T pc, T* lds_dst) {
+__device__ inline bool pre_child_core(const EvalArgs& a, int c, int l, int tile, int s, int ps, const Coef& cf,
+                                      const T q[M], const T msib[M], const T mown[M], T pc, T qout[M]) {
     T u[M];
 #pragma unroll
     for (int x = 0; x < M; ++x) u[x] = q[x] * msib[x];
@@ -615,9 +730,22 @@ __device__ inline void pre_child(const EvalArgs& a, int c, int l, int tile, int 
 #pragma unroll
         for (int y = 0; y < M; ++y) mx = fmax(mx, qc[y]);
         const int e = (mx > T(0)) ? exp_of(mx) : 0;
+#pragma unroll
+        for (int y = 0; y < M; ++y) qout[y] = pow2_scale(qc[y], -e);
+        return true;
+    }
+    return false;
+}
+
+// q~_c goes to LDS (lds_dst) or to memory
+template <int M, typename T, bool HESS, bool NH>
+__device__ inline void pre_child(const EvalArgs& a, int c, int l, int tile, int s, int ps, const Coef& cf,
+                                 const T q[M], const T msib[M], const T mown[M], T pc, T* lds_dst) {
+    T qc[M];
+    if (pre_child_core<M, T, HESS, NH>(a, c, l, tile, s, ps, cf, q, msib, mown, pc, qc)) {
         T* out = lds_dst ? lds_dst : static_cast<T*>(a.qv) + vec_off(a, c, tile, M) + ps;
 #pragma unroll
-        for (int y = 0; y < M; ++y) out[y * TP] = pow2_scale(qc[y], -e);
+        for (int y = 0; y < M; ++y) out[y * TP] = qc[y];
     }
 }
 
@@ -673,19 +801,78 @@ __device__ inline void pre_node(const EvalArgs& a, int4 nd, int l, int tile, int
     pre_child<M, T, HESS, NH>(a, nd.z, l, tile, s, ps, cf, q, mi, mj, pj_, dj);
 }
 
-#ifndef PG_PRE_NS64
-#define PG_PRE_NS64 16
-#endif
-#ifndef PG_PRE_WPE64
-#define PG_PRE_WPE64 1
-#endif
-template <typename T>
-__host__ __device__ constexpr int pre_slots(int M) {
-    return (M * M <= TP && sizeof(T) == 8) ? PG_PRE_NS64 : node_slots(M);
+// Clade part of the pre-order pass (after the top): q of a clade root comes
+// from memory, q of a second child (or of a first child with a tip sibling)
+// from registers, q of a first child with an internal sibling from the
+// stack.  CLADE_DEPTH entries are in flight: an entry's loads are issued
+// CLADE_DEPTH - 1 entries before it is processed.
+constexpr int CLADE_DEPTH = 4;
+
+template <int M, typename T, bool HESS, bool NH>
+__device__ inline void pre_clade_node(const EvalArgs& a, int4 nd, int l, int tile, int s, int ps, const Coef& cf,
+                                      const PreRaw<M, T>& r, T acc[M], T* stk, int& sp) {
+    T q[M];
+    if (nd.w & CL_ROOT) {
+#pragma unroll
+        for (int x = 0; x < M; ++x) q[x] = r.q[x];
+    } else if (nd.w & CL_STACK) {
+        stack_pop<M, T>(stk, sp, q);
+    } else {
+#pragma unroll
+        for (int x = 0; x < M; ++x) q[x] = acc[x];
+    }
+    T m0[M], m1[M], q0[M], q1[M];
+    child_finish<M, T>(a, nd.y, l, r.ri, m0);
+    child_finish<M, T>(a, nd.z, l, r.rj, m1);
+    const T p0 = (nd.y < a.n_tips) ? r.ri.v[0] : r.pi_;
+    const T p1 = (nd.z < a.n_tips) ? r.rj.v[0] : r.pj_;
+    const bool in0 = pre_child_core<M, T, HESS, NH>(a, nd.y, l, tile, s, ps, cf, q, m1, m0, p0, q0);
+    const bool in1 = pre_child_core<M, T, HESS, NH>(a, nd.z, l, tile, s, ps, cf, q, m0, m1, p1, q1);
+    // the second child's subtree comes next, then the first child's
+    if (in1) {
+        if (in0) stack_push<M, T>(stk, sp, q0);
+#pragma unroll
+        for (int x = 0; x < M; ++x) acc[x] = q1[x];
+    } else if (in0) {
+#pragma unroll
+        for (int x = 0; x < M; ++x) acc[x] = q0[x];
+    }
 }
-template <typename T>
-__host__ __device__ constexpr int pre_waves(int M) {
-    return M * M <= TP ? (sizeof(T) == 8 ? PG_PRE_WPE64 : 4) : 1;
+
+template <int M, typename T, bool HESS, bool NH>
+__device__ inline void pre_clades(const EvalArgs& a, const int4* lds, int l, int tile, int s, int ps, int ns,
+                                  const Coef& cf, T* stk) {
+    static_assert(RowMat<M>::value, "clade walks use row-distributed matrices");
+    const int beg = a.cl_pre_off[ns], end = a.cl_pre_off[ns + 1];
+    const int n = end - beg;
+    if (n <= 0) return;
+    int sp = 0;
+    T acc[M];
+#pragma unroll
+    for (int x = 0; x < M; ++x) acc[x] = T(0);
+    // entry i of the walk is list entry end - 1 - i
+    int4 nd[CLADE_DEPTH];
+    PreRaw<M, T> raw[CLADE_DEPTH];
+#pragma unroll
+    for (int j = 0; j < CLADE_DEPTH; ++j) {
+        if (j < n) {
+            nd[j] = clade_at(a, lds, a.cl_pre, end - 1 - j);
+            pre_load<M, T>(a, nd[j], l, tile, s, ps, raw[j], (nd[j].w & CL_ROOT) != 0);
+        }
+    }
+    for (int i0 = 0; i0 < n; i0 += CLADE_DEPTH) {
+#pragma unroll
+        for (int j = 0; j < CLADE_DEPTH; ++j) {
+            const int i = i0 + j;
+            if (i < n) {
+                pre_clade_node<M, T, HESS, NH>(a, nd[j], l, tile, s, ps, cf, raw[j], acc, stk, sp);
+                if (i + CLADE_DEPTH < n) {
+                    nd[j] = clade_at(a, lds, a.cl_pre, end - 1 - (i + CLADE_DEPTH));
+                    pre_load<M, T>(a, nd[j], l, tile, s, ps, raw[j], (nd[j].w & CL_ROOT) != 0);
+                }
+            }
+        }
+    }
 }
 
 // NH: non-homogeneous model (Q of each child's branch from a table); a
@@ -704,7 +891,7 @@ __device__ inline void pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
         // the category-0 tile of each pattern block also forms its logL part
         if (l == 0 && ns == 0) logl_block_part(a, pb, ps, r);
     }
-    stage_schedule(a, lds_sched);
+    stage_schedule(a, lds_sched, a.n_cl ? a.cl_pre : nullptr);
     T* top = top_buffer<T>(a, lds_sched);
     // top region first: each slot issues its next level's loads (children
     // messages of the post-order pass) before the LDS-only barrier; the last
@@ -774,6 +961,11 @@ __device__ inline void pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
             }
         }
         __syncthreads();
+    }
+    // clades last: their roots' q were written above; the stack reuses the
+    // top region's LDS
+    if constexpr (RowMat<M>::value) {
+        if (a.n_cl) pre_clades<M, T, HESS, NH>(a, lds_sched, l, tile, s, ps, ns, cf, clade_stack<M, T>(a, top, ns, ps));
     }
 }
 
@@ -912,7 +1104,7 @@ hipError_t launch_pmat(const EvalArgs& a, int precision, hipStream_t st) {
 
 template <int M, typename T>
 static hipError_t post_launch(const EvalArgs& a, hipStream_t st) {
-    post_kernel<M, T><<<a.n_tiles, node_slots(M) * TP, sched_lds_bytes(a), st>>>(a);
+    post_kernel<M, T><<<a.n_tiles, node_slots(M) * TP, post_lds_bytes(a, sizeof(T) == 4 ? PG_FP32 : PG_FP64), st>>>(a);
     return hipGetLastError();
 }
 
@@ -928,7 +1120,7 @@ hipError_t launch_logl(const EvalArgs& a, hipStream_t st) {
 
 template <int M, typename T>
 static hipError_t pre_launch(const EvalArgs& a, hipStream_t st, bool hess) {
-    const size_t lds = sched_lds_bytes(a) + top_lds_bytes(a, sizeof(T));
+    const size_t lds = pre_lds_bytes(a, sizeof(T) == 4 ? PG_FP32 : PG_FP64);
     const dim3 grid(a.n_tiles), block(pre_slots<T>(M) * TP);
     if (a.n_models) {
         if (hess) pre_kernel<M, T, true, true><<<grid, block, lds, st>>>(a);
@@ -994,9 +1186,14 @@ int pmat_blocks(const EvalArgs& a) {
 int traversal_blocks(const EvalArgs& a) { return a.n_tiles; }
 int gsum_total_blocks(const EvalArgs& a) { return gsum_blocks(a.n_branches) + 1; }
 
-size_t post_lds_bytes(const EvalArgs& a) { return sched_lds_bytes(a); }
+size_t post_lds_bytes(const EvalArgs& a, int precision) {
+    const size_t es = precision == PG_FP32 ? 4 : 8;
+    return sched_lds_bytes(a) + clade_stack_bytes(a, node_slots(a.M), es);
+}
 size_t pre_lds_bytes(const EvalArgs& a, int precision) {
-    return sched_lds_bytes(a) + top_lds_bytes(a, precision == PG_FP32 ? 4 : 8);
+    const size_t es = precision == PG_FP32 ? 4 : 8;
+    return sched_lds_bytes(a) +
+           std::max(top_lds_bytes(a, es), clade_stack_bytes(a, pre_node_slots(a.M, precision), es));
 }
 
 template <int M, typename T>

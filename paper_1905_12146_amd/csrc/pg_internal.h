@@ -27,6 +27,38 @@ constexpr int SCHED_LDS_MAX = 32768;
 // level it admits (one node per node slot).
 constexpr int TOP_LDS_MAX = 32768;
 constexpr int TOP_LEVEL_MAX_NODES = 16;
+// Node slots of the pre-order kernel (FP64 small M: fewer, heavier slots).
+#ifndef PG_PRE_NS64
+#define PG_PRE_NS64 16
+#endif
+#ifndef PG_PRE_WPE64
+#define PG_PRE_WPE64 1
+#endif
+template <typename T>
+__host__ __device__ constexpr int pre_slots(int M) {
+    return (M * M <= TP && sizeof(T) == 8) ? PG_PRE_NS64 : node_slots(M);
+}
+template <typename T>
+__host__ __device__ constexpr int pre_waves(int M) {
+    return M * M <= TP ? (sizeof(T) == 8 ? PG_PRE_WPE64 : 4) : 1;
+}
+inline int pre_node_slots(int M, int precision) {
+    return precision == PG_FP32 ? pre_slots<float>(M) : pre_slots<double>(M);
+}
+// Clades (small M, FP64 and FP32): the maximal subtrees below the root with
+// at most CLADE_CAP internal nodes are walked depth first, each by one node
+// slot, with a per-slot LDS stack; the other internal nodes (the top) keep
+// the level-synchronous walk.  Entry flags of a clade walk:
+#ifndef PG_CLADE_CAP
+#define PG_CLADE_CAP 32
+#endif
+constexpr int CLADE_CAP = PG_CLADE_CAP;
+constexpr int CL_STACK = 1;  // post: push the node's message; pre: pop its q
+constexpr int CL_ROOT = 2;   // clade root: pre reads its q from memory
+// LDS budget of the clade stacks of one workgroup, and of a traversal
+// workgroup's dynamic LDS in all (the schedule is left in memory beyond it).
+constexpr int CLADE_STACK_MAX = 32768;
+constexpr int LDS_BLOCK_MAX = 61440;
 
 __host__ __device__ inline int gsum_blocks(int n_branches) {
     return (n_branches + GS_BRANCHES - 1) / GS_BRANCHES;
@@ -53,6 +85,18 @@ struct EvalArgs {
     int top_level;                     // first level of the pre-order top region
                                        // (n_levels: none)
     int top_nodes;                     // nodes in the top region (LDS blocks)
+    int n_sched;                       // entries of sched (the top nodes when
+                                       // clades are walked, else all N-1)
+    // clade walks: entries {node, first child, second child, CL_* flags} in
+    // post order within each clade (the child with more internal nodes
+    // first), clades grouped by node slot; the pre-order kernel walks its
+    // list backwards.  The two kernels' lists differ when their slot counts do.
+    int n_cl;                          // entries per list (0: no clades)
+    int cl_depth;                      // stack blocks (M x TP) per node slot
+    const int4* cl_post;               // [n_cl]
+    const int* cl_post_off;            // [node_slots(M) + 1] slot ranges
+    const int4* cl_pre;                // [n_cl]
+    const int* cl_pre_off;             // [pre slots + 1]
     const double* Q64;                 // [M][M]
     const double* Q2_64;               // [M][M] Q*Q
     const double* pi64;                // [M]
@@ -108,7 +152,10 @@ constexpr size_t MF_QOP_BYTES = 3 * 8 * 64 * 16;
 
 // Kernel launchers (kernels.hip).  Each returns a hipError_t from the launch.
 bool kernel_supported(int M, int precision);
-inline size_t sched_lds_bytes(const EvalArgs& a) { return a.sched_lds ? sizeof(int4) * (a.n_tips - 1) : 0; }
+inline size_t sched_lds_bytes(const EvalArgs& a) { return a.sched_lds ? sizeof(int4) * (a.n_sched + a.n_cl) : 0; }
+inline size_t clade_stack_bytes(const EvalArgs& a, int slots, size_t elem) {
+    return elem * (size_t)slots * a.cl_depth * a.M * TP;
+}
 inline size_t top_lds_bytes(const EvalArgs& a, size_t elem) { return elem * (size_t)a.top_nodes * a.M * TP; }
 hipError_t launch_pmat(const EvalArgs& a, int precision, hipStream_t s);
 hipError_t launch_post(const EvalArgs& a, int precision, hipStream_t s);
@@ -137,7 +184,7 @@ struct BatchLaunch {
 int pmat_blocks(const EvalArgs& a);
 int traversal_blocks(const EvalArgs& a);
 int gsum_total_blocks(const EvalArgs& a);
-size_t post_lds_bytes(const EvalArgs& a);
+size_t post_lds_bytes(const EvalArgs& a, int precision);
 size_t pre_lds_bytes(const EvalArgs& a, int precision);
 hipError_t launch_batch(const BatchLaunch& b, hipStream_t s);
 

@@ -229,7 +229,7 @@ int run_group(pg_server* s, std::vector<Item>& items) {
         pm += pmat_blocks(it.args);
         tr += traversal_blocks(it.args);
         gs += gsum_total_blocks(it.args);
-        post_lds = std::max(post_lds, post_lds_bytes(it.args));
+        post_lds = std::max(post_lds, post_lds_bytes(it.args, s->precision));
         pre_lds = std::max(pre_lds, pre_lds_bytes(it.args, s->precision));
     }
     const size_t off_t = 0;

@@ -42,14 +42,25 @@ __device__ inline unsigned long long tip_mask(const EvalArgs& a, unsigned code, 
 
 // Level-ordered schedule entry idx: {node, child 0, child 1, 0}, from LDS
 // when the schedule was staged there.
+// An LDS read through an LDS-typed pointer: a select between the staged
+// copy and global memory would otherwise become one generic (flat) load,
+// whose wait also drains every outstanding global load.
+typedef __attribute__((address_space(3))) const int lds_int;
+__device__ inline int4 lds_entry(const int4* lds, int idx) {
+    const lds_int* p = (const lds_int*)(lds + idx);
+    return make_int4(p[0], p[1], p[2], p[3]);
+}
+
 __device__ inline int4 sched_at(const EvalArgs& a, const int4* lds, int idx) {
-    return a.sched_lds ? lds[idx] : a.sched[idx];
+    if (a.sched_lds) return lds_entry(lds, idx);
+    return a.sched[idx];
 }
 
 // Entry idx of a clade list cl (this kernel's), staged after the level
 // schedule.
 __device__ inline int4 clade_at(const EvalArgs& a, const int4* lds, const int4* cl, int idx) {
-    return a.sched_lds ? lds[a.n_sched + idx] : cl[idx];
+    if (a.sched_lds) return lds_entry(lds, a.n_sched + idx);
+    return cl[idx];
 }
 
 // Stages the level schedule and the kernel's clade list (cl, n_cl entries;

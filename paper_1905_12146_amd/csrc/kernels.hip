@@ -471,25 +471,84 @@ __device__ inline void stack_pop(T* stk, int& sp, T v[M]) {
     for (int x = 0; x < M; ++x) v[x] = stk[(sp * M + x) * TP];
 }
 
-// Loads of one post-order clade entry: tip children and the node's own
-// matrix entry (internal children's messages are in registers or LDS).
+// Tip message with a row-distributed P (pe = this lane's entry): the
+// observed state's column, read from the lane holding entry (x, code);
+// ambiguity codes (rare) sum the allowed columns, masks from the LDS copy.
 template <int M, typename T>
-struct PostCladeRaw {
-    ChildRaw<M, T> r0, r1;
-    T pk;
+__device__ inline void tip_message(unsigned code, T pe, const unsigned long long* lmask, T out[M]) {
+    const int col = code < (unsigned)M ? (int)code : 0;
+#pragma unroll
+    for (int x = 0; x < M; ++x) out[x] = __shfl(pe, x * M + col, TP);
+    if (__any(code >= (unsigned)M)) {
+        T amb[M];
+        row_masked_rows<M, T>(pe, lmask[code & 255u], amb);
+        if (code >= (unsigned)M) {
+#pragma unroll
+            for (int x = 0; x < M; ++x) out[x] = amb[x];
+        }
+    }
+}
+
+// The clade walks issue every load of an entry whatever its children are
+// (a tip child's message slot and an internal child's code read valid,
+// unused addresses), so each entry has the same number of loads in flight
+// and the wait before an entry's use counts only the loads issued after it,
+// leaving the prefetched entries in flight.
+template <int M, typename T>
+struct ChildAll {
+    T v[M];         // message of an internal child
+    T pe;           // this lane's entry of the child's P
+    unsigned code;  // tip code
 };
 
 template <int M, typename T>
-__device__ inline void post_clade_load(const EvalArgs& a, int4 nd, int l, int tile, int s, int ps,
-                                       PostCladeRaw<M, T>& r) {
-    if (nd.y < a.n_tips) child_load<M, T>(a, nd.y, l, tile, s, ps, r.r0);
-    if (nd.z < a.n_tips) child_load<M, T>(a, nd.z, l, tile, s, ps, r.r1);
-    r.pk = load_row_entry<M, T>(pmat_of<M, T>(a, nd.x, l), ps);
+__device__ inline void child_load_all(const EvalArgs& a, int c, int l, int tile, int s, int ps, ChildAll<M, T>& r) {
+    const bool tip = c < a.n_tips;
+    const T* src = static_cast<const T*>(a.msg) + (tip ? (size_t)0 : vec_off(a, c, tile, M)) + ps;
+#pragma unroll
+    for (int x = 0; x < M; ++x) r.v[x] = src[x * TP];
+    r.code = a.codes[(size_t)(tip ? c : 0) * a.S_pad + s];
+    r.pe = pmat_of<M, T>(a, c, l)[ps];
+}
+
+template <int M, typename T>
+__device__ inline void child_msg_all(const EvalArgs& a, int c, const ChildAll<M, T>& r,
+                                     const unsigned long long* lmask, T out[M]) {
+    if (c < a.n_tips) {
+        tip_message<M, T>(r.code, r.pe, lmask, out);
+    } else {
+#pragma unroll
+        for (int x = 0; x < M; ++x) out[x] = r.v[x];
+    }
+}
+
+// Loads of one post-order clade entry: the children's codes and matrix
+// entries and the node's own entry (internal children's messages are in
+// registers or on the stack).
+template <int M, typename T>
+struct PostCladeRaw {
+    unsigned code0, code1;
+    T pe0, pe1, pk;
+};
+
+template <int M, typename T>
+__device__ inline void post_clade_load(const EvalArgs& a, int4 nd, int l, int s, int ps, PostCladeRaw<M, T>& r) {
+    r.code0 = a.codes[(size_t)(nd.y < a.n_tips ? nd.y : 0) * a.S_pad + s];
+    r.code1 = a.codes[(size_t)(nd.z < a.n_tips ? nd.z : 0) * a.S_pad + s];
+    r.pe0 = pmat_of<M, T>(a, nd.y, l)[ps];
+    r.pe1 = pmat_of<M, T>(a, nd.z, l)[ps];
+    r.pk = pmat_of<M, T>(a, nd.x, l)[ps];
+}
+
+// Copy of the code -> state mask table in LDS (ambiguity codes).
+__device__ inline void stage_masks(const EvalArgs& a, unsigned long long* lmask) {
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) lmask[i] = a.masks[i];
+    __syncthreads();
 }
 
 template <int M, typename T>
 __device__ inline void post_clades(const EvalArgs& a, const int4* lds, int l, int tile, int s, int ps, int ns,
-                                   T* stk, int& esum) {
+                                   T* stk, const unsigned long long* lmask, int& esum) {
     static_assert(RowMat<M>::value, "clade walks use row-distributed matrices");
     const int beg = a.cl_post_off[ns], end = a.cl_post_off[ns + 1];
     if (beg >= end) return;
@@ -497,20 +556,20 @@ __device__ inline void post_clades(const EvalArgs& a, const int4* lds, int l, in
     T acc[M];
 #pragma unroll
     for (int x = 0; x < M; ++x) acc[x] = T(0);
-    int4 nd = clade_at(a, lds, a.cl_post, beg);
+    // entries past the end reload the last one, so every iteration issues
+    // the same loads; an entry is read one iteration before its loads
+    auto entry = [&](int i) { return clade_at(a, lds, a.cl_post, min(i, end - 1)); };
+    int4 nd = entry(beg);
+    int4 nn = entry(beg + 1);
     PostCladeRaw<M, T> cur;
-    post_clade_load<M, T>(a, nd, l, tile, s, ps, cur);
+    post_clade_load<M, T>(a, nd, l, s, ps, cur);
     for (int i = beg;; ++i) {
-        const bool more = i + 1 < end;
-        int4 nn = nd;
+        const int4 n2 = entry(i + 2);
         PostCladeRaw<M, T> nxt;
-        if (more) {
-            nn = clade_at(a, lds, a.cl_post, i + 1);
-            post_clade_load<M, T>(a, nn, l, tile, s, ps, nxt);
-        }
+        post_clade_load<M, T>(a, nn, l, s, ps, nxt);
         T m0[M], m1[M], p[M], mk[M];
         if (nd.y < a.n_tips) {
-            child_finish<M, T>(a, nd.y, l, cur.r0, m0);
+            tip_message<M, T>(cur.code0, cur.pe0, lmask, m0);
         } else if (nd.z < a.n_tips) {
 #pragma unroll
             for (int x = 0; x < M; ++x) m0[x] = acc[x];
@@ -518,7 +577,7 @@ __device__ inline void post_clades(const EvalArgs& a, const int4* lds, int l, in
             stack_pop<M, T>(stk, sp, m0);
         }
         if (nd.z < a.n_tips) {
-            child_finish<M, T>(a, nd.z, l, cur.r1, m1);
+            tip_message<M, T>(cur.code1, cur.pe1, lmask, m1);
         } else {
 #pragma unroll
             for (int x = 0; x < M; ++x) m1[x] = acc[x];
@@ -534,8 +593,9 @@ __device__ inline void post_clades(const EvalArgs& a, const int4* lds, int l, in
 #pragma unroll
             for (int x = 0; x < M; ++x) acc[x] = mk[x];
         }
-        if (!more) break;
+        if (i + 1 >= end) break;
         nd = nn;
+        nn = n2;
         cur = nxt;
     }
 }
@@ -551,8 +611,10 @@ __device__ inline void post_body(const EvalArgs& a, int tile, int4* lds_sched) {
     if constexpr (RowMat<M>::value) {
         // clades first: the top's lowest level reads the clade roots' messages
         if (a.n_cl) {
+            __shared__ unsigned long long lmask[256];
+            stage_masks(a, lmask);
             post_clades<M, T>(a, lds_sched, l, tile, s, ps, ns,
-                              clade_stack<M, T>(a, top_buffer<T>(a, lds_sched), ns, ps), esum);
+                              clade_stack<M, T>(a, top_buffer<T>(a, lds_sched), ns, ps), lmask, esum);
             __syncthreads();
         }
     }
@@ -806,11 +868,31 @@ __device__ inline void pre_node(const EvalArgs& a, int4 nd, int l, int tile, int
 // from registers, q of a first child with an internal sibling from the
 // stack.  CLADE_DEPTH entries are in flight: an entry's loads are issued
 // CLADE_DEPTH - 1 entries before it is processed.
-constexpr int CLADE_DEPTH = 4;
+#ifndef PG_CLADE_DEPTH
+#define PG_CLADE_DEPTH 2
+#endif
+constexpr int CLADE_DEPTH = PG_CLADE_DEPTH;
+
+template <int M, typename T>
+struct PreCladeRaw {
+    T q[M];  // clade root: q from memory
+    ChildAll<M, T> c0, c1;
+};
+
+template <int M, typename T>
+__device__ inline void pre_clade_load(const EvalArgs& a, int4 nd, int l, int tile, int s, int ps,
+                                      PreCladeRaw<M, T>& r) {
+    const T* src = static_cast<const T*>(a.qv) + ((nd.w & CL_ROOT) ? vec_off(a, nd.x, tile, M) : (size_t)0) + ps;
+#pragma unroll
+    for (int x = 0; x < M; ++x) r.q[x] = src[x * TP];
+    child_load_all<M, T>(a, nd.y, l, tile, s, ps, r.c0);
+    child_load_all<M, T>(a, nd.z, l, tile, s, ps, r.c1);
+}
 
 template <int M, typename T, bool HESS, bool NH>
 __device__ inline void pre_clade_node(const EvalArgs& a, int4 nd, int l, int tile, int s, int ps, const Coef& cf,
-                                      const PreRaw<M, T>& r, T acc[M], T* stk, int& sp) {
+                                      const PreCladeRaw<M, T>& r, const unsigned long long* lmask, T acc[M],
+                                      T* stk, int& sp) {
     T q[M];
     if (nd.w & CL_ROOT) {
 #pragma unroll
@@ -822,12 +904,10 @@ __device__ inline void pre_clade_node(const EvalArgs& a, int4 nd, int l, int til
         for (int x = 0; x < M; ++x) q[x] = acc[x];
     }
     T m0[M], m1[M], q0[M], q1[M];
-    child_finish<M, T>(a, nd.y, l, r.ri, m0);
-    child_finish<M, T>(a, nd.z, l, r.rj, m1);
-    const T p0 = (nd.y < a.n_tips) ? r.ri.v[0] : r.pi_;
-    const T p1 = (nd.z < a.n_tips) ? r.rj.v[0] : r.pj_;
-    const bool in0 = pre_child_core<M, T, HESS, NH>(a, nd.y, l, tile, s, ps, cf, q, m1, m0, p0, q0);
-    const bool in1 = pre_child_core<M, T, HESS, NH>(a, nd.z, l, tile, s, ps, cf, q, m0, m1, p1, q1);
+    child_msg_all<M, T>(a, nd.y, r.c0, lmask, m0);
+    child_msg_all<M, T>(a, nd.z, r.c1, lmask, m1);
+    const bool in0 = pre_child_core<M, T, HESS, NH>(a, nd.y, l, tile, s, ps, cf, q, m1, m0, r.c0.pe, q0);
+    const bool in1 = pre_child_core<M, T, HESS, NH>(a, nd.z, l, tile, s, ps, cf, q, m0, m1, r.c1.pe, q1);
     // the second child's subtree comes next, then the first child's
     if (in1) {
         if (in0) stack_push<M, T>(stk, sp, q0);
@@ -841,7 +921,7 @@ __device__ inline void pre_clade_node(const EvalArgs& a, int4 nd, int l, int til
 
 template <int M, typename T, bool HESS, bool NH>
 __device__ inline void pre_clades(const EvalArgs& a, const int4* lds, int l, int tile, int s, int ps, int ns,
-                                  const Coef& cf, T* stk) {
+                                  const Coef& cf, T* stk, const unsigned long long* lmask) {
     static_assert(RowMat<M>::value, "clade walks use row-distributed matrices");
     const int beg = a.cl_pre_off[ns], end = a.cl_pre_off[ns + 1];
     const int n = end - beg;
@@ -850,27 +930,29 @@ __device__ inline void pre_clades(const EvalArgs& a, const int4* lds, int l, int
     T acc[M];
 #pragma unroll
     for (int x = 0; x < M; ++x) acc[x] = T(0);
-    // entry i of the walk is list entry end - 1 - i
+    // entry i of the walk is list entry end - 1 - i; entries past the end
+    // reload the last one, so every step issues the same loads
+    // reload the last one, so every step issues the same loads; an entry is
+    // read one step before its loads are issued
+    auto entry = [&](int i) { return clade_at(a, lds, a.cl_pre, end - 1 - min(i, n - 1)); };
     int4 nd[CLADE_DEPTH];
-    PreRaw<M, T> raw[CLADE_DEPTH];
+    PreCladeRaw<M, T> raw[CLADE_DEPTH];
 #pragma unroll
     for (int j = 0; j < CLADE_DEPTH; ++j) {
-        if (j < n) {
-            nd[j] = clade_at(a, lds, a.cl_pre, end - 1 - j);
-            pre_load<M, T>(a, nd[j], l, tile, s, ps, raw[j], (nd[j].w & CL_ROOT) != 0);
-        }
+        nd[j] = entry(j);
+        pre_clade_load<M, T>(a, nd[j], l, tile, s, ps, raw[j]);
     }
+    int4 ne = entry(CLADE_DEPTH);
+    // only the processing depends on the step being in range: the refills
+    // are unconditional, so the ring's registers carry no merged values
     for (int i0 = 0; i0 < n; i0 += CLADE_DEPTH) {
 #pragma unroll
         for (int j = 0; j < CLADE_DEPTH; ++j) {
-            const int i = i0 + j;
-            if (i < n) {
-                pre_clade_node<M, T, HESS, NH>(a, nd[j], l, tile, s, ps, cf, raw[j], acc, stk, sp);
-                if (i + CLADE_DEPTH < n) {
-                    nd[j] = clade_at(a, lds, a.cl_pre, end - 1 - (i + CLADE_DEPTH));
-                    pre_load<M, T>(a, nd[j], l, tile, s, ps, raw[j], (nd[j].w & CL_ROOT) != 0);
-                }
-            }
+            if (i0 + j < n) pre_clade_node<M, T, HESS, NH>(a, nd[j], l, tile, s, ps, cf, raw[j], lmask, acc, stk, sp);
+            const int4 ne2 = entry(i0 + j + CLADE_DEPTH + 1);
+            nd[j] = ne;
+            pre_clade_load<M, T>(a, nd[j], l, tile, s, ps, raw[j]);
+            ne = ne2;
         }
     }
 }
@@ -965,7 +1047,11 @@ __device__ inline void pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
     // clades last: their roots' q were written above; the stack reuses the
     // top region's LDS
     if constexpr (RowMat<M>::value) {
-        if (a.n_cl) pre_clades<M, T, HESS, NH>(a, lds_sched, l, tile, s, ps, ns, cf, clade_stack<M, T>(a, top, ns, ps));
+        if (a.n_cl) {
+            __shared__ unsigned long long lmask[256];
+            stage_masks(a, lmask);
+            pre_clades<M, T, HESS, NH>(a, lds_sched, l, tile, s, ps, ns, cf, clade_stack<M, T>(a, top, ns, ps), lmask);
+        }
     }
 }
 

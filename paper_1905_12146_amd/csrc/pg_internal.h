@@ -57,7 +57,10 @@ constexpr int CL_STACK = 1;  // post: push the node's message; pre: pop its q
 constexpr int CL_ROOT = 2;   // clade root: pre reads its q from memory
 // LDS budget of the clade stacks of one workgroup, and of a traversal
 // workgroup's dynamic LDS in all (the schedule is left in memory beyond it).
-constexpr int CLADE_STACK_MAX = 32768;
+#ifndef PG_CLADE_STACK_MAX
+#define PG_CLADE_STACK_MAX 32768
+#endif
+constexpr int CLADE_STACK_MAX = PG_CLADE_STACK_MAX;
 constexpr int LDS_BLOCK_MAX = 61440;
 
 __host__ __device__ inline int gsum_blocks(int n_branches) {

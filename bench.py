@@ -38,19 +38,22 @@ METRIC = "logL+full-gradient evals/sec, N=1000 4-state; p50/p99 served latency"
 def byte_model(n_tips, n_patterns, n_states, n_cats, elem_bytes):
     """Algorithmic HBM bytes per launch of the two traversal kernels.
 
-    V = K m S elem_bytes is one partial vector; I' = N - 2 internal non-root
-    nodes.  Post-order: each stored message is written once and read once
-    by the parent (2 I' V), tips (N S bytes of codes) and transition
-    matrices |P| read once.  Pre-order: q of each internal non-root node
-    read once and written once, each message read once more (3 I' V), tips
-    and |P| read once.
+    V = K m S elem_bytes is one message vector; I' = N - 2 internal non-root
+    nodes.  The messages of one pass do not fit on chip, so the post-order
+    kernel writes each once and the pre-order kernel reads each once (I' V
+    each); both read the tip codes (N S bytes) and the transition matrices
+    |P|, and the pre-order kernel writes one gradient partial per branch
+    and tile (8 (2N - 2) K ceil(S / 16) bytes).  Everything else (children's
+    messages within the post-order walk, the pre-order vectors q) can stay
+    on chip and is not counted.
     """
     V = n_cats * n_states * n_patterns * elem_bytes
     I = n_tips - 2
     P = (2 * n_tips - 2) * n_cats * n_states * n_states * elem_bytes
     tips = n_tips * n_patterns
-    return {"post": 2 * I * V + tips + P, "pre": 3 * I * V + tips + P,
-            "per_node_post": 2 * V, "per_node_pre": 3 * V, "V": V, "P": P, "tips": tips}
+    partials = 8 * (2 * n_tips - 2) * n_cats * ((n_patterns + 15) // 16)
+    return {"post": I * V + tips + P, "pre": I * V + tips + P + partials,
+            "per_node_post": V, "per_node_pre": V, "V": V, "P": P, "tips": tips, "partials": partials}
 
 
 def cpu_model():

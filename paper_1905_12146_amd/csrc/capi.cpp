@@ -458,7 +458,8 @@ int upload(pg_ctx* c) {
     if ((r = ensure_buf(c, "masks", sizeof(unsigned long long) * 256))) return r;
     // traversal schedule: clades for the small-M FP64 / FP32 kernels, with a
     // smaller cap when a deep clade's stack would not fit CLADE_STACK_MAX
-    const int ns_post = node_slots(M), ns_pre = split ? ns_post : pre_node_slots(M, c->precision);
+    const int ns_post = split ? node_slots(M) : post_node_slots(M, c->precision);
+    const int ns_pre = split ? ns_post : pre_node_slots(M, c->precision);
     Schedule sc;
     {
         int cap = (!split && M * M <= TP) ? CLADE_CAP : 0;

@@ -11,9 +11,10 @@
 // pattern block), so one node's data for one tile is a single contiguous run.
 //
 // Work decomposition: a workgroup owns one tile and walks the whole tree for
-// it, level by level (nodes of equal height are independent).  Its threads
-// are NS node slots x TP pattern lanes (NS = node_slots(M)); a barrier
-// separates levels.  Tiles
+// it: for small M the clades depth first (one node slot each) and the nodes
+// above them level by level, otherwise every node level by level (nodes of
+// equal height are independent; a barrier separates levels).  Its threads
+// are NS node slots x TP pattern lanes (post_slots / pre_slots).  Tiles
 // never communicate, so a pass needs no grid-wide synchronisation.
 //
 // Rescaling is per node, pattern and category, by an exact power of two.
@@ -602,7 +603,7 @@ __device__ inline void post_clades(const EvalArgs& a, const int4* lds, int l, in
 
 template <int M, typename T>
 __device__ inline void post_body(const EvalArgs& a, int tile, int4* lds_sched) {
-    constexpr int NS = node_slots(M);
+    constexpr int NS = post_slots<T>(M);
     const int l = tile / a.n_pb, pb = tile % a.n_pb;
     const int ps = threadIdx.x % TP, ns = threadIdx.x / TP;
     const int s = pb * TP + ps;
@@ -1126,13 +1127,13 @@ __global__ void __launch_bounds__(256) pmat_lds_batch(const EvalArgs* __restrict
 }
 
 template <int M, typename T>
-__global__ void __launch_bounds__(node_slots(M) * TP) __attribute__((amdgpu_waves_per_eu(RowMat<M>::value ? 4 : 1)))
+__global__ void __launch_bounds__(post_slots<T>(M) * TP) __attribute__((amdgpu_waves_per_eu(RowMat<M>::value ? 4 : 1)))
 post_kernel(EvalArgs a) {
     extern __shared__ int4 lds_dyn[];
     post_body<M, T>(a, blockIdx.x, lds_dyn);
 }
 template <int M, typename T>
-__global__ void __launch_bounds__(node_slots(M) * TP) __attribute__((amdgpu_waves_per_eu(RowMat<M>::value ? 4 : 1)))
+__global__ void __launch_bounds__(post_slots<T>(M) * TP) __attribute__((amdgpu_waves_per_eu(RowMat<M>::value ? 4 : 1)))
 post_batch(const EvalArgs* __restrict__ reqs, const int2* __restrict__ map) {
     extern __shared__ int4 lds_dyn[];
     const int2 m = map[blockIdx.x];
@@ -1190,7 +1191,7 @@ hipError_t launch_pmat(const EvalArgs& a, int precision, hipStream_t st) {
 
 template <int M, typename T>
 static hipError_t post_launch(const EvalArgs& a, hipStream_t st) {
-    post_kernel<M, T><<<a.n_tiles, node_slots(M) * TP, post_lds_bytes(a, sizeof(T) == 4 ? PG_FP32 : PG_FP64), st>>>(a);
+    post_kernel<M, T><<<a.n_tiles, post_slots<T>(M) * TP, post_lds_bytes(a, sizeof(T) == 4 ? PG_FP32 : PG_FP64), st>>>(a);
     return hipGetLastError();
 }
 
@@ -1274,7 +1275,7 @@ int gsum_total_blocks(const EvalArgs& a) { return gsum_blocks(a.n_branches) + 1;
 
 size_t post_lds_bytes(const EvalArgs& a, int precision) {
     const size_t es = precision == PG_FP32 ? 4 : 8;
-    return sched_lds_bytes(a) + clade_stack_bytes(a, node_slots(a.M), es);
+    return sched_lds_bytes(a) + clade_stack_bytes(a, post_node_slots(a.M, precision), es);
 }
 size_t pre_lds_bytes(const EvalArgs& a, int precision) {
     const size_t es = precision == PG_FP32 ? 4 : 8;
@@ -1288,7 +1289,7 @@ static hipError_t batch_launch(const BatchLaunch& b, hipStream_t st) {
         if constexpr (M <= 8) pmat_reg_batch<M, T><<<b.pmat_blocks, 256, 0, st>>>(b.reqs, b.pmat_map);
         else pmat_lds_batch<M, T><<<b.pmat_blocks, 256, 0, st>>>(b.reqs, b.pmat_map);
     }
-    post_batch<M, T><<<b.trav_blocks, node_slots(M) * TP, b.post_lds, st>>>(b.reqs, b.trav_map);
+    post_batch<M, T><<<b.trav_blocks, post_slots<T>(M) * TP, b.post_lds, st>>>(b.reqs, b.trav_map);
     pre_batch<M, T><<<b.trav_blocks, pre_slots<T>(M) * TP, b.pre_lds, st>>>(b.reqs, b.trav_map);
     gsum_batch<<<b.gsum_blocks, GS_THREADS, 0, st>>>(b.reqs, b.gsum_map);
     return hipGetLastError();

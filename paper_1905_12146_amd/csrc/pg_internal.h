@@ -45,6 +45,16 @@ __host__ __device__ constexpr int pre_waves(int M) {
 inline int pre_node_slots(int M, int precision) {
     return precision == PG_FP32 ? pre_slots<float>(M) : pre_slots<double>(M);
 }
+// Node slots of the post-order kernel: as many as the pre-order kernel's for
+// small M, so both walk the same clade lists (the pre-order walk then reads
+// first the messages the post-order walk wrote last, while still cached).
+template <typename T>
+__host__ __device__ constexpr int post_slots(int M) {
+    return M * M <= TP ? pre_slots<T>(M) : node_slots(M);
+}
+inline int post_node_slots(int M, int precision) {
+    return precision == PG_FP32 ? post_slots<float>(M) : post_slots<double>(M);
+}
 // Clades (small M, FP64 and FP32): the maximal subtrees below the root with
 // at most CLADE_CAP internal nodes are walked depth first, each by one node
 // slot, with a per-slot LDS stack; the other internal nodes (the top) keep
@@ -97,7 +107,7 @@ struct EvalArgs {
     int n_cl;                          // entries per list (0: no clades)
     int cl_depth;                      // stack blocks (M x TP) per node slot
     const int4* cl_post;               // [n_cl]
-    const int* cl_post_off;            // [node_slots(M) + 1] slot ranges
+    const int* cl_post_off;            // [post slots + 1] slot ranges
     const int4* cl_pre;                // [n_cl]
     const int* cl_pre_off;             // [pre slots + 1]
     const double* Q64;                 // [M][M]

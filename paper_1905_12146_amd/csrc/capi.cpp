@@ -460,14 +460,33 @@ int upload(pg_ctx* c) {
     // smaller cap when a deep clade's stack would not fit CLADE_STACK_MAX
     const int ns_post = split ? node_slots(M) : post_node_slots(M, c->precision);
     const int ns_pre = split ? ns_post : pre_node_slots(M, c->precision);
+    // The clade cap is chosen per tree among a few sizes: larger clades mean
+    // fewer level-walk iterations above them (each ends at a barrier), but
+    // fewer clades to balance over the slots and deeper stacks.  Cost
+    // estimate: the busiest pre-order slot's clade entries plus twice the
+    // top's level iterations; caps whose stacks exceed CLADE_STACK_MAX are
+    // skipped.
     Schedule sc;
-    {
-        int cap = (!split && M * M <= TP) ? CLADE_CAP : 0;
-        build_schedule(c, cap, ns_post, ns_pre, sc);
-        while (cap > 0 && es * std::max(ns_post, ns_pre) * sc.depth * M * TP > (size_t)CLADE_STACK_MAX) {
-            cap = cap * 3 / 4;
-            build_schedule(c, cap, ns_post, ns_pre, sc);
+    if (!split && M * M <= TP) {
+        long best = -1;
+        for (int cap : {64, 48, 32, 24, 16}) {
+            if (cap > CLADE_CAP) continue;
+            Schedule t;
+            build_schedule(c, cap, ns_post, ns_pre, t);
+            if (es * std::max(ns_post, ns_pre) * t.depth * M * TP > (size_t)CLADE_STACK_MAX) continue;
+            long busiest = 0, top_iters = 0;
+            for (int b = 0; b < ns_pre; ++b) busiest = std::max<long>(busiest, t.cl_pre_off[b + 1] - t.cl_pre_off[b]);
+            for (size_t h = 0; h + 1 < t.level_off.size(); ++h)
+                top_iters += (t.level_off[h + 1] - t.level_off[h] + ns_pre - 1) / ns_pre;
+            const long cost = busiest + 2 * top_iters;
+            if (best < 0 || cost < best) {
+                best = cost;
+                sc = std::move(t);
+            }
         }
+        if (best < 0) build_schedule(c, 0, ns_post, ns_pre, sc);
+    } else {
+        build_schedule(c, 0, ns_post, ns_pre, sc);
     }
     const int n_top = (int)sc.level_nodes.size(), n_cl = (int)sc.cl_post.size();
     const bool one_list = ns_post == ns_pre;

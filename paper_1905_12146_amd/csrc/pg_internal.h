@@ -56,11 +56,12 @@ inline int post_node_slots(int M, int precision) {
     return precision == PG_FP32 ? post_slots<float>(M) : post_slots<double>(M);
 }
 // Clades (small M, FP64 and FP32): the maximal subtrees below the root with
-// at most CLADE_CAP internal nodes are walked depth first, each by one node
-// slot, with a per-slot LDS stack; the other internal nodes (the top) keep
-// the level-synchronous walk.  Entry flags of a clade walk:
+// at most a cap of internal nodes (chosen per tree, at most CLADE_CAP) are
+// walked depth first, each by one node slot, with a per-slot LDS stack; the
+// other internal nodes (the top) keep the level-synchronous walk.  Entry
+// flags of a clade walk:
 #ifndef PG_CLADE_CAP
-#define PG_CLADE_CAP 32
+#define PG_CLADE_CAP 64
 #endif
 constexpr int CLADE_CAP = PG_CLADE_CAP;
 constexpr int CL_STACK = 1;  // post: push the node's message; pre: pop its q

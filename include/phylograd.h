@@ -84,9 +84,11 @@ extern "C" {
 
 typedef struct pg_ctx pg_ctx;
 
-/* Create a context on HIP device `device` with precision PG_FP64 or
- * PG_FP32.  No device memory is allocated until the first evaluation.
- * Fails with PG_E_DEVICE when the device does not exist or is not gfx950. */
+/* Create a context on HIP device `device` with precision PG_FP64, PG_FP32
+ * or PG_SPLIT_BF16 (any other value: PG_E_UNSUPPORTED).  No device memory is
+ * allocated until the first evaluation.  Fails with PG_E_DEVICE when the
+ * device does not exist or is not gfx950.  *out is NULL on failure; the
+ * caller owns the context and frees it with pg_destroy. */
 int pg_create(int device, int precision, pg_ctx** out);
 
 /* Release the context and all its device memory (waits for its stream). */
@@ -107,8 +109,12 @@ int pg_set_stream(pg_ctx* ctx, void* hip_stream);
  * patterns. Errors: PG_E_INVALID (NULL, N < 2), PG_E_TREE. */
 int pg_set_tree(pg_ctx* ctx, int32_t n_tips, const int32_t* parent);
 
-/* Site patterns.  tip_masks[N*S]: row v (tip v), column s, bit x = state x
- * allowed, 2 <= m <= 64; weights[S] finite and >= 0.  Needs the tree.
+/* Site patterns (Section 2.1: sites are independent, a tip's partial
+ * vector is the indicator of its observed state, or of the allowed states
+ * when it is partly observed or missing).  tip_masks[N*S], row-major: row v
+ * (tip v), column s, bit x = state x allowed, 2 <= m <= 64; weights[S]
+ * finite and >= 0 (a pattern's multiplicity in logL = sum_s w_s log L_s).
+ * Both arrays are copied.  Needs the tree.
  * Errors: PG_E_STATE (no tree), PG_E_INVALID, PG_E_PATTERNS (empty mask,
  * a bit >= m, more than 255 - m distinct partial-ambiguity masks). */
 int pg_set_patterns(pg_ctx* ctx, int32_t n_patterns, int32_t n_states,
@@ -117,8 +123,12 @@ int pg_set_patterns(pg_ctx* ctx, int32_t n_patterns, int32_t n_states,
 /* Substitution model (Sections 2.1 and 2.6).  Q[m*m] row-major generator,
  * root_freqs[m] a probability vector, cat_rates[K] >= 0 and
  * cat_weights[K] a probability vector (the discrete rate categories
- * gamma_l and Pr(gamma_l)).  Compiled state counts: m = 4 and m = 20.
- * Errors: PG_E_INVALID, PG_E_MODEL, PG_E_UNSUPPORTED. */
+ * gamma_l and Pr(gamma_l)), 1 <= K <= 64.  All arrays are copied.  Compiled
+ * state counts: m = 4 and m = 20 for PG_FP64 and PG_FP32; any
+ * 2 <= m <= 64 for PG_SPLIT_BF16.  Errors: PG_E_INVALID (NULL), PG_E_MODEL
+ * (negative off-diagonal, a row not summing to 0, a frequency or weight
+ * vector not summing to 1, a negative rate), PG_E_UNSUPPORTED (m without a
+ * kernel for the context's precision). */
 int pg_set_model(pg_ctx* ctx, int32_t n_states, const double* Q,
                  const double* root_freqs, int32_t n_cats,
                  const double* cat_rates, const double* cat_weights);
@@ -150,18 +160,27 @@ int pg_set_branch_models(pg_ctx* ctx, int32_t n_models, const double* Q, const i
 int pg_logL_update(pg_ctx* ctx, int32_t n, const int32_t* branches, const double* t_new, double* logL);
 
 /* One evaluation from host memory: t[2N-2] branch lengths in, *logL and,
- * unless grad == NULL, grad[2N-2] = dlogL/dt_b out.  Blocks until done.
+ * unless grad == NULL, grad[2N-2] = dlogL/dt_b out.  logL is the post-order
+ * pass (Section 2.3, Eqs. postOrderPartialUpdate and rootInnerProduct, with
+ * categories Eq. discreteRateLikelihood); the gradient is the pre-order pass
+ * (Section 2.4, Eq. preOrderUpdate) with every branch's derivative formed in
+ * the same traversal (Section 2.5 Eq. singleRateCaseGradient, Section 2.6
+ * Eq. GradientWithGamma).  Blocks until done.
  * Errors: PG_E_STATE, PG_E_INVALID (t), PG_E_ZERO_LIK (*logL = -inf, grad
  * left unspecified), PG_E_DEVICE, PG_E_OOM. */
 int pg_logL_and_grad(pg_ctx* ctx, const double* t, double* logL, double* grad);
 
-/* Post-order pass only (transition matrices, pruning, root): *logL out.
- * The partial vectors stay resident on the device for a later pg_grad. */
+/* Post-order pass only (transition matrices, pruning, root; Section 2.3,
+ * Eqs. postOrderPartialUpdate and rootInnerProduct): *logL out.  Blocks.
+ * The partial vectors stay resident on the device for a later pg_grad.
+ * Errors as pg_logL_and_grad. */
 int pg_logL(pg_ctx* ctx, const double* t, double* logL);
 
-/* Pre-order pass on the partials left by the last successful pg_logL (or
- * pg_logL_and_grad): grad[2N-2] out.  PG_E_STATE if there are none or the
- * tree, patterns or model changed since. */
+/* Pre-order pass fused with the gradient (Section 2.4 Eq. preOrderUpdate,
+ * Sections 2.5-2.6 Eqs. singleRateCaseGradient and GradientWithGamma) on
+ * the partials left by the last successful pg_logL (or pg_logL_and_grad):
+ * grad[2N-2] (host, caller-allocated) out.  Blocks.  PG_E_STATE if there are
+ * none or the tree, patterns or model changed since. */
 int pg_grad(pg_ctx* ctx, double* grad);
 
 /* Diagonal of the Hessian, d2 logL / dt_b^2, Section 2.7 Eq. (Hessian),
@@ -170,7 +189,8 @@ int pg_grad(pg_ctx* ctx, double* grad);
  * PG_E_UNSUPPORTED on a PG_SPLIT_BF16 context. */
 int pg_hessian_diag(pg_ctx* ctx, double* grad, double* hess);
 
-/* Device-pointer variant: d_t[2N-2] (FP64, device), d_logL[1] and
+/* Device-pointer variant of pg_logL_and_grad (same passes and sections):
+ * d_t[2N-2] (FP64, device), d_logL[1] and
  * d_grad[2N-2] (device, d_grad may be NULL) are read and written
  * asynchronously on the context's stream; pointers must stay valid until
  * that stream reaches this work.  No host synchronisation.  Branch lengths
@@ -180,7 +200,8 @@ int pg_hessian_diag(pg_ctx* ctx, double* grad, double* hess);
 int pg_logL_and_grad_device(pg_ctx* ctx, const double* d_t, double* d_logL,
                             double* d_grad);
 
-/* Device-pointer pre-order pass: the gradient of the partials left by the
+/* Device-pointer pre-order pass (as pg_grad, Sections 2.4-2.6): the
+ * gradient of the partials left by the
  * last evaluation (pg_logL_and_grad_device with d_grad == NULL, pg_logL,
  * ...) is written to d_grad[2N-2] (device) asynchronously on the context's
  * stream; no host synchronisation.  This is the backward of an autograd

@@ -3,19 +3,24 @@
 Workload (default): Yule tree with N=1000 tips, branch lengths ~ Exp(mean
 0.01), random non-reversible 4-state Q, 4 discrete-gamma categories
 (shape 0.5), 2000 site patterns simulated down the tree, weights ~ U{1..20},
-per-node rescaling, gradient for all 1998 branches; FP64.
+per-node rescaling, gradient for all 1998 branches; FP64.  --workload C5
+runs the 20-state workload (N=500, S=3000), C4 the 61-state codon workload
+on the split-BF16 matrix-core path.
 
 A step is one full evaluation through the C-ABI device entry point
 (transition matrices, post-order pass, root, pre-order pass with the fused
 gradient, per-branch reduction) on inputs already resident in HBM.
 
-    python bench.py [--steps K] [--warmup W] [--precision fp64|fp32]
+    python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|split]
+                    [--workload C2|C4|C5]
 
-Prints one JSON line.  ``roofline`` reports the dominant kernel's
-algorithmic bytes per launch over its mean duration, measured with HIP
-events recorded by the library on the stream the kernel runs on;
-``cpu_baseline`` times the CPU oracle (naive O(N^2) gradient) on a bounded
-sample of branches and scales it to one full evaluation.
+Prints one JSON line: `value` is K evaluations over the wall clock around
+them; `eval_time_us` the median / p5 / p95 of per-evaluation HIP-event
+durations; ``roofline`` the dominant kernel's bytes per launch (the
+accounting of `survey_bytes`, with the on-chip lower bound beside it) over
+its mean duration, measured with HIP events recorded by the library on the
+stream the kernel runs on; ``cpu_baseline`` the CPU oracle on bounded
+samples (see `cpu_baseline`).
 """
 from __future__ import annotations
 
@@ -35,25 +40,42 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "logL+full-gradient evals/sec, N=1000 4-state; p50/p99 served latency"
 
 
-def byte_model(n_tips, n_patterns, n_states, n_cats, elem_bytes):
-    """Algorithmic HBM bytes per launch of the two traversal kernels.
+def survey_bytes(n_tips, n_patterns, n_states, n_cats, elem_bytes):
+    """Bytes the method moves per evaluation (the accounting used for `frac`).
 
-    V = K m S elem_bytes is one message vector; I' = N - 2 internal non-root
-    nodes.  The messages of one pass do not fit on chip, so the post-order
-    kernel writes each once and the pre-order kernel reads each once (I' V
-    each); both read the tip codes (N S bytes) and the transition matrices
-    |P|, and the pre-order kernel writes one gradient partial per branch
-    and tile (8 (2N - 2) K ceil(S / 16) bytes).  Everything else (children's
-    messages within the post-order walk, the pre-order vectors q) can stay
-    on chip and is not counted.
+    V = K m S elem_bytes is one partial vector, I' = N - 2 internal non-root
+    nodes.  Each stored message (P_k p_k) is written once and read twice (by
+    the parent in the post-order pass and in the pre-order pass), each
+    pre-order vector q is written once and read once, and each pass reads
+    the tip codes (N S bytes) and the transition matrices |P|:
+        evaluation = 5 I' V + 2 N S + 2 |P|,
+        post-order kernel = 2 I' V + N S + |P|  (message write, parent read),
+        pre-order kernel  = 3 I' V + N S + |P|  (message read, q write and read).
     """
     V = n_cats * n_states * n_patterns * elem_bytes
     I = n_tips - 2
     P = (2 * n_tips - 2) * n_cats * n_states * n_states * elem_bytes
     tips = n_tips * n_patterns
+    return {"post": 2 * I * V + tips + P, "pre": 3 * I * V + tips + P,
+            "eval": 5 * I * V + 2 * tips + 2 * P, "V": V, "P": P, "tips": tips}
+
+
+def onchip_bytes(n_tips, n_patterns, n_states, n_cats, elem_bytes):
+    """Lower bound when children's messages and every q stay on chip.
+
+    The messages of one pass do not fit on chip, so the post-order kernel
+    writes each once and the pre-order kernel reads each once (I' V each);
+    both read the tip codes and |P|, and the pre-order kernel writes one
+    gradient partial per branch and tile (8 (2N - 2) K ceil(S / 16) bytes).
+    The depth-first clade walks of the 4-state kernels approach this."""
+    V = n_cats * n_states * n_patterns * elem_bytes
+    I = n_tips - 2
+    P = (2 * n_tips - 2) * n_cats * n_states * n_states * elem_bytes
+    tips = n_tips * n_patterns
     partials = 8 * (2 * n_tips - 2) * n_cats * ((n_patterns + 15) // 16)
-    return {"post": I * V + tips + P, "pre": I * V + tips + P + partials,
-            "per_node_post": V, "per_node_pre": V, "V": V, "P": P, "tips": tips, "partials": partials}
+    post = I * V + tips + P
+    pre = I * V + tips + P + partials
+    return {"post": post, "pre": pre, "eval": post + pre}
 
 
 def cpu_model():
@@ -66,24 +88,98 @@ def cpu_model():
     return platform.processor()
 
 
-def cpu_baseline(w, n_branches_sample):
-    """The CPU oracle's naive O(N^2) gradient on a sample of branches."""
+def cpu_cores():
+    """Host cores this process may use, at most 16 (one GPU's CPU share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_args(w, patterns=None):
+    masks, weights = w.tip_masks(), w.weights
+    if patterns is not None:
+        masks, weights = masks[:, patterns], weights[patterns]
+    return (w.parent, w.t, w.Q, w.pi, w.rates, w.cat_weights, masks, weights)
+
+
+def _linear_chunk(job):
+    """One worker of the all-core O(N) run: its share of the patterns."""
+    from threadpoolctl import threadpool_limits
     import oracle
-    args = (w.parent, w.t, w.Q, w.pi, w.rates, w.cat_weights, w.tip_masks(), w.weights)
+    w, patterns = job
+    with threadpool_limits(1):
+        r = oracle.linear_gradient(*_oracle_args(w, patterns))
+    return r["logL"], r["grad"]
+
+
+def cpu_baseline(w, budget_s=10.0):
+    """The CPU oracle timed on the host cores, on bounded samples.
+
+    Run before the GPU is touched (its all-core leg forks worker processes).
+    value: the naive O(N^2) oracle gradient (the parity reference): one
+    pruning pass per branch on a sample of branches, scaled to all 2N - 2.
+    others: the paper's O(N) post/pre-order gradient on one core and on all
+    cores (patterns split over worker processes), the pruning logL alone on
+    one core, and central finite differences (two logL per branch, the
+    paper's "Numeric" gradient of Section 5.1) on a sample of branches,
+    scaled to all branches.  BLAS threads are held to one per process."""
+    import multiprocessing as mp
+
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    host = f"{cpu_model()}, os.cpu_count()={os.cpu_count()}"
+    B = len(w.t)
+    args = _oracle_args(w)
     rng = np.random.default_rng(0)
-    sample = sorted(rng.choice(len(w.t), size=n_branches_sample, replace=False).tolist())
-    t0 = time.perf_counter()
-    oracle.naive_gradient(*args, branches=[])
-    t_logL = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.naive_gradient(*args, branches=sample)
-    t_sample = time.perf_counter() - t0 - t_logL
-    per_branch = t_sample / n_branches_sample
-    per_eval = t_logL + per_branch * len(w.t)
-    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"naive O(N^2) oracle gradient on {n_branches_sample} of {len(w.t)} branches "
-                      f"plus one logL ({t_logL + t_sample:.1f} s), scaled to one full evaluation "
-                      f"({per_eval:.0f} s); host {cpu_model()}, os.cpu_count()={os.cpu_count()}"}
+    out = {}
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        oracle.log_likelihood(*args)
+        t_logL = time.perf_counter() - t0
+        n_naive = int(max(2, min(B, budget_s / max(t_logL, 1e-3))))
+        sample = sorted(rng.choice(B, size=n_naive, replace=False).tolist())
+        t0 = time.perf_counter()
+        oracle.naive_gradient(*args, branches=sample)
+        t_naive = time.perf_counter() - t0
+        per_eval = t_logL + (t_naive - t_logL) / n_naive * B
+        t0 = time.perf_counter()
+        oracle.linear_gradient(*args)
+        t_lin1 = time.perf_counter() - t0
+        n_fd = int(max(1, min(B, 0.5 * budget_s / max(2 * t_logL, 1e-3))))
+        fd_sample = sorted(rng.choice(B, size=n_fd, replace=False).tolist())
+        h = 1e-6
+        t0 = time.perf_counter()
+        oracle.central_fd_gradient(*args, h=h, branches=fd_sample)
+        t_fd = time.perf_counter() - t0
+    cores = cpu_cores()
+    chunks = [c for c in np.array_split(np.arange(w.n_patterns), cores) if len(c)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(len(chunks)) as pool:
+        pool.map(_linear_chunk, [(w, chunks[0][:16])] * len(chunks))  # start the workers
+        t0 = time.perf_counter()
+        pool.map(_linear_chunk, [(w, c) for c in chunks])
+        t_linN = time.perf_counter() - t0
+    others = [
+        {"kind": "oracle_linear_O(N)", "value": round(1.0 / t_lin1, 4), "unit": "evals/s", "cores": 1,
+         "sample": f"one full evaluation ({t_lin1:.1f} s)"},
+        {"kind": "oracle_linear_O(N)", "value": round(1.0 / t_linN, 4), "unit": "evals/s",
+         "cores": len(chunks),
+         "sample": f"one full evaluation, {w.n_patterns} patterns split over {len(chunks)} processes "
+                   f"({t_linN:.2f} s)"},
+        {"kind": "oracle_pruning_logL", "value": round(1.0 / t_logL, 4), "unit": "logL evals/s", "cores": 1,
+         "sample": f"one post-order logL ({t_logL:.2f} s)"},
+        {"kind": "central_fd_gradient", "value": 1.0 / (t_fd / n_fd * B), "unit": "evals/s", "cores": 1,
+         "sample": f"central differences h={h:g} on {n_fd} of {B} branches ({t_fd:.1f} s), "
+                   f"scaled to all branches ({t_fd / n_fd * B:.0f} s)"},
+    ]
+    out = {"value": 1.0 / per_eval, "unit": "evals/s", "cores": 1, "kind": "oracle",
+           "sample": f"naive O(N^2) oracle gradient (one pruning pass per branch) on {n_naive} of {B} "
+                     f"branches ({t_naive:.1f} s), scaled to one full evaluation ({per_eval:.0f} s)",
+           "host": host, "others": others}
+    return out
 
 
 def calibrate_copy():
@@ -152,28 +248,51 @@ def serving_bench(args):
     with Server(0, B.PG_FP32, budget, 1) as srv:
         cap = run_stream(srv, with_rate(1e9), workloads, calls=args.calls)
     capacity = cap["completed"] / cap["wall_s"]
+
+    def serve(qps, slots, budget_bytes):
+        with Server(0, B.PG_FP32, budget_bytes, slots) as srv:
+            r = run_stream(srv, with_rate(qps), workloads, calls=args.calls)
+            st = srv.stats()
+        r.pop("results")
+        row = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items() if k != "errors"}
+        row["errors"] = len(r["errors"])
+        row["max_batch"] = st["max_batch"]
+        row["peak_gb"] = round(st["peak_bytes"] / 2 ** 30, 2)
+        row["peak_held_gb"] = round(st["peak_held"] / 2 ** 30, 2)
+        row["max_waiting"] = st["max_waiting"]
+        # keeps up: completed requests per second within 10% of the arrival rate
+        row["keeps_up"] = bool(r["requests_per_s"] >= 0.9 * qps)
+        return row
+
+    # arrival rates rise until the one-at-a-time server falls behind them,
+    # then one more
     runs = []
+    behind = 0
     for f in [float(x) for x in args.qps_factors.split(",") if x]:
         qps = f * capacity
-        row = {"qps_factor": f, "qps": round(qps, 2)}
-        for mode, slots in (("batched", args.max_sessions), ("one_at_a_time", 1)):
-            with Server(0, B.PG_FP32, budget, slots) as srv:
-                r = run_stream(srv, with_rate(qps), workloads, calls=args.calls)
-                st = srv.stats()
-            r.pop("results")
-            row[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items() if k != "errors"}
-            row[mode]["errors"] = len(r["errors"])
-            row[mode]["max_batch"] = st["max_batch"]
-            row[mode]["peak_gb"] = round(st["peak_bytes"] / 2 ** 30, 2)
-            row[mode]["max_waiting"] = st["max_waiting"]
+        row = {"qps_factor": f, "qps": round(qps, 2),
+               "batched": serve(qps, args.max_sessions, budget),
+               "one_at_a_time": serve(qps, 1, budget)}
         runs.append(row)
+        print(json.dumps({"serving_progress": row["qps_factor"],
+                          "one_at_a_time_keeps_up": row["one_at_a_time"]["keeps_up"],
+                          "batched_keeps_up": row["batched"]["keeps_up"]}), file=sys.stderr, flush=True)
+        if not row["one_at_a_time"]["keeps_up"]:
+            behind += 1
+            if behind >= 2:
+                break
+    # admission that binds: a budget that holds only a few sessions at once,
+    # at the highest arrival rate
+    tight_gb = args.tight_budget_gb
+    tight = {"budget_gb": tight_gb, "qps": runs[-1]["qps"],
+             "batched": serve(runs[-1]["qps"], args.max_sessions, int(tight_gb * (1 << 30)))}
     out = {"metric": "served gradient calls: p50/p99 request latency and throughput",
            "workload": f"{args.requests} requests, N~U{{100..2000}}, S~U{{500..5000}}, 4-state, K=4, FP32, "
                        f"{args.calls} calls each, Poisson arrivals",
            "budget_gb": args.budget_gb, "max_sessions": args.max_sessions,
            "one_at_a_time_capacity_req_per_s": round(capacity, 2),
            "capacity_run": {"wall_s": round(cap["wall_s"], 3), "calls_per_s": round(cap["calls_per_s"], 1)},
-           "generation_s": round(gen_s, 1), "runs": runs}
+           "generation_s": round(gen_s, 1), "runs": runs, "tight_budget": tight}
     print(json.dumps(out), flush=True)
 
 
@@ -219,11 +338,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", choices=["fp64", "fp32", "split"], default=None,
                     help="fp64 / fp32 (default fp64 for C2), split = split-BF16 matrix cores (C4)")
-    ap.add_argument("--workload", choices=["C2", "C4"], default="C2",
-                    help="C2: N=1000 4-state (headline); C4: N=256 61-state codon, split-BF16")
+    ap.add_argument("--workload", choices=["C2", "C4", "C5"], default="C2",
+                    help="C2: N=1000 4-state (headline); C4: N=256 61-state codon, split-BF16; "
+                         "C5: N=500 20-state, 3000 patterns")
     ap.add_argument("--timing-steps", type=int, default=30)
-    ap.add_argument("--cpu-branches", type=int, default=20,
-                    help="branches of the CPU oracle sample (0 disables the CPU leg)")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="CPU work per sampled oracle leg (0 disables the CPU baseline)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (HBM counter calibration)")
     ap.add_argument("--serving", action="store_true",
@@ -231,8 +351,11 @@ def main():
                          "vs one request at a time)")
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--calls", type=int, default=10)
-    ap.add_argument("--qps-factors", default="0.25,0.5,0.75,0.9,1.2",
-                    help="arrival rates as multiples of the one-at-a-time capacity")
+    ap.add_argument("--qps-factors", default="0.5,1,1.5,2,3,4,6,8,12",
+                    help="arrival rates as multiples of the one-at-a-time capacity (the sweep "
+                         "stops after the one-at-a-time server has fallen behind twice)")
+    ap.add_argument("--tight-budget-gb", type=float, default=2.0,
+                    help="HBM budget of the extra run in which admission binds")
     ap.add_argument("--budget-gb", type=float, default=32.0)
     ap.add_argument("--max-sessions", type=int, default=64)
     ap.add_argument("--updates", action="store_true",
@@ -252,14 +375,19 @@ def main():
               "(the pattern-sharded multi-GPU layout is a design, not built)", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-
-    from paper_1905_12146_amd import binding as B
     from synth import make_workload
 
     if args.precision is None:
         args.precision = "split" if args.workload == "C4" else "fp64"
     w = make_workload(args.workload)
+    # the CPU legs run first: the all-core leg forks, which must happen
+    # before this process touches the GPU
+    cpu = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
+
+    import torch
+
+    from paper_1905_12146_amd import binding as B
+
     N, S, m, K = w.n_tips, w.n_patterns, w.n_states, w.n_cats
     prec = {"fp64": B.PG_FP64, "fp32": B.PG_FP32, "split": B.PG_SPLIT_BF16}[args.precision]
     es = 8 if prec == B.PG_FP64 else 4
@@ -292,7 +420,21 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     value = args.steps / elapsed
 
-    # per-kernel durations: HIP events on the context's stream, one pair per kernel
+    # per-evaluation durations: a HIP event pair around each evaluation on
+    # the context's stream (torch's current stream here)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        step()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ev_us = np.array([e0.elapsed_time(e1) * 1e3 for e0, e1 in evs])
+    eval_us = {"median": round(float(np.median(ev_us)), 2), "p5": round(float(np.percentile(ev_us, 5)), 2),
+               "p95": round(float(np.percentile(ev_us, 95)), 2), "n": len(ev_us)}
+
+    # per-kernel durations: HIP events recorded by the library on the
+    # context's stream, one pair per kernel launch
     ctx.set_timing(True)
     for _ in range(args.timing_steps):
         step()
@@ -300,16 +442,30 @@ def main():
     ctx.set_timing(False)
     times = ctx.timing()
     avg_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in times.items()}
-    bm = byte_model(N, S, m, K, es)
+    sb = survey_bytes(N, S, m, K, es)
+    ob = onchip_bytes(N, S, m, K, es)
     dom = max(("post", "pre"), key=lambda k: avg_ms[k])
-    achieved = bm[dom] / (avg_ms[dom] * 1e-3) / 1e9 if avg_ms[dom] > 0 else 0.0
+
+    def rate(nbytes, ms):
+        return nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+
+    achieved = rate(sb[dom], avg_ms[dom])
+    med_ms = eval_us["median"] * 1e-3
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic_record(dom, args.precision, args.workload),
-                "bytes_per_launch": bm[dom], "avg_us": round(avg_ms[dom] * 1e3, 2),
+                "byte_model": "5 I'V + 2 N S + 2 |P| per evaluation; post 2 I'V + N S + |P|, "
+                              "pre 3 I'V + N S + |P|",
+                "bytes_per_launch": sb[dom], "avg_us": round(avg_ms[dom] * 1e3, 2),
                 "kernels_avg_us": {k: round(v * 1e3, 2) for k, v in avg_ms.items()},
-                "eval_bytes": bm["post"] + bm["pre"],
-                "eval_frac": round((bm["post"] + bm["pre"]) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                "kernels_frac": {k: round(rate(sb[k], avg_ms[k]) / HBM_PEAK_GBS, 4) for k in ("post", "pre")},
+                "eval_bytes": sb["eval"],
+                "eval_frac": round(rate(sb["eval"], med_ms) / HBM_PEAK_GBS, 4),
+                "onchip_model": {"what": "lower bound with children's messages and q kept on chip",
+                                 "bytes_per_launch": {k: ob[k] for k in ("post", "pre")},
+                                 "frac": round(rate(ob[dom], avg_ms[dom]) / HBM_PEAK_GBS, 4),
+                                 "eval_bytes": ob["eval"],
+                                 "eval_frac": round(rate(ob["eval"], med_ms) / HBM_PEAK_GBS, 4)}}
 
     if prec == B.PG_SPLIT_BF16:
         # executed BF16 matrix-core work of the dominant kernel: 16x16x32
@@ -336,10 +492,11 @@ def main():
                                   f"{len(w.t)} branch gradients",
                       "n_tips": N, "n_patterns": S, "n_states": m, "n_cats": K,
                       "precision": args.precision},
+           "eval_time_us": eval_us,
            "roofline": roofline}
     ctx.close()
-    if args.cpu_branches > 0:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_branches)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

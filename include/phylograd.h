@@ -243,20 +243,27 @@ int pg_eigensystem(int32_t m, const double* Q, double* V, double* Vinv, double* 
 
 /* ---- serving: many gradient sessions with continuous batching --------
  *
- * A server owns a worker thread and an HBM budget.  pg_server_open creates a
- * session (its own tree, patterns and model, checked as by pg_set_*), which
- * waits in arrival order until its device footprint (pg_footprint_bytes)
- * fits next to the admitted sessions and fewer than max_sessions are
- * admitted.  pg_server_submit queues one evaluation (logL and, if
- * want_grad, the gradient) with host branch lengths t[2N-2]; the worker runs
- * the oldest queued call of every admitted session together as one batch
- * (one launch per kernel for all of them), and calls that arrive meanwhile
- * join the next batch.  A call gives the same result, bit for bit, whether
- * it runs alone or in a batch.  pg_server_wait blocks until a call is done,
- * copies logL and grad (caller-allocated, 2N-2), and reports the time from
- * submit to completion.  pg_server_close lets the session's queued calls
- * finish, then frees its device memory, which admits waiting sessions.
- * Server functions are thread-safe. */
+ * A server owns a worker thread, an upload thread and an HBM budget.
+ * pg_server_open creates a session (its own tree, patterns and model,
+ * checked as by pg_set_*, and planned on the caller's thread), which waits
+ * in arrival order until the device bytes it may take (its buffers rounded
+ * to the session memory pool's 64 KiB granule, plus 1/8 for the pool's
+ * reuse of larger blocks) fit next to the admitted sessions and fewer than
+ * max_sessions are admitted.  An admitted session's buffers are allocated
+ * and its inputs copied by the upload thread on a stream of its own while
+ * batches keep running; it is then charged what the pool handed out.  The
+ * pool's blocks in use plus cached never exceed the budget.
+ * pg_server_submit queues one evaluation (logL and, if want_grad, the
+ * gradient) with host branch lengths t[2N-2]; the worker runs the oldest
+ * queued call of every admitted session together as one batch (one launch
+ * per kernel for all of them), and calls that arrive meanwhile join the next
+ * batch.  A call gives the same result, bit for bit, whether it runs alone or
+ * in a batch.  pg_server_wait blocks until a call is done, copies logL and
+ * grad (caller-allocated, 2N-2), and reports the time from submit to
+ * completion.  pg_server_close lets the session's queued calls finish, then
+ * frees its device memory, which admits waiting sessions.  If a session's
+ * upload fails, its queued calls complete with that error.  Server functions
+ * are thread-safe. */
 typedef struct pg_server pg_server;
 
 /* Errors: PG_E_INVALID (NULL, budget <= 0, max_sessions < 1), PG_E_DEVICE,
@@ -296,7 +303,10 @@ int pg_server_close(pg_server* srv, int64_t session);
 #define PG_SRV_IN_USE_BYTES   6  /* device bytes of admitted sessions    */
 #define PG_SRV_PEAK_BYTES     7  /* largest in-use bytes so far          */
 #define PG_SRV_MAX_WAITING    8  /* longest admission queue so far       */
-#define PG_SRV_STAT_COUNT     9
+#define PG_SRV_PEAK_HELD      9  /* largest device bytes held by the session
+                                    memory pool (in use plus cached), never
+                                    above the budget                      */
+#define PG_SRV_STAT_COUNT     10
 int pg_server_stats(pg_server* srv, int64_t* out, int32_t n);
 
 #ifdef __cplusplus

@@ -279,7 +279,7 @@ def pg_eigensystem(Q):
 # -- serving -------------------------------------------------------------------
 
 SRV_STAT_NAMES = ("steps", "calls", "max_batch", "admitted_total", "admitted_now", "waiting_now",
-                  "in_use_bytes", "peak_bytes", "max_waiting")
+                  "in_use_bytes", "peak_bytes", "max_waiting", "peak_held")
 
 
 def _check_srv(srv, code):

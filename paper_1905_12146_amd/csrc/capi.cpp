@@ -37,9 +37,8 @@ struct pg_ctx {
     bool tree_set = false;
     int n_tips = 0;
     std::vector<int> parent;
-    std::vector<int2> children;
-    std::vector<int> level_off, level_nodes;
-    std::vector<int> height;                  // [2N-1] tips 0, cherries 1, ...
+    std::vector<Kids> children;               // [2N-1], set for internal nodes
+    TreeLevels lv;                            // internal nodes by height
 
     // patterns
     bool patterns_set = false;
@@ -65,8 +64,13 @@ struct pg_ctx {
     std::vector<double> bm_Q, bm_Q2, bm_qnorm;
     std::vector<int> bm_model;
 
+    // traversal plan of the tree for the model's state count
+    TraversalPlan plan;
+    bool plan_stale = true;
+
     // device state
     bool dev_stale = true;        // host inputs changed since the last upload
+    bool host_copies = false;     // copies from the host vectors may be in flight
     bool have_partials = false;   // post-order pass results resident
     // partial re-evaluation: host copy of the branch lengths of the resident
     // partials (host-pointer evaluations only) and per-node exponents
@@ -127,15 +131,16 @@ int ensure_buf(pg_ctx* c, const char* name, size_t bytes) {
         b.bytes = 0;
     }
     void* p = nullptr;
+    size_t granted = std::max<size_t>(bytes, 256);
     if (c->allocator) {
-        p = c->allocator->acquire(std::max<size_t>(bytes, 256));
+        p = c->allocator->acquire(granted, &granted);
         if (!p) return fail(c, PG_E_OOM, "device pool allocation failed");
     } else {
-        hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 256));
+        hipError_t e = hipMalloc(&p, granted);
         if (e != hipSuccess) return hip_fail(c, e, "hipMalloc");
     }
     b.ptr = p;
-    b.bytes = std::max<size_t>(bytes, 256);
+    b.bytes = granted;
     return PG_OK;
 }
 
@@ -210,191 +215,12 @@ void prepare_split_model(pg_ctx* c) {
                 }
 }
 
-// Internal nodes grouped by height (tips have height 0); nodes of one level
-// have no ancestor relation, so a level is processed in parallel and the
-// levels in increasing order form a post-order (decreasing: a pre-order).
-void build_levels(pg_ctx* c) {
-    const int N = c->n_tips, n_nodes = 2 * N - 1;
-    std::vector<int> height(n_nodes, 0);
-    // internal nodes: repeat relaxation in label-free order via explicit stack
-    std::vector<int> order;
-    order.reserve(N - 1);
-    std::vector<int> stack{n_nodes - 1};
-    std::vector<char> expanded(n_nodes, 0);
-    while (!stack.empty()) {
-        int v = stack.back();
-        if (v < N) { stack.pop_back(); continue; }
-        if (!expanded[v]) {
-            expanded[v] = 1;
-            stack.push_back(c->children[v].x);
-            stack.push_back(c->children[v].y);
-        } else {
-            stack.pop_back();
-            height[v] = 1 + std::max(height[c->children[v].x], height[c->children[v].y]);
-            order.push_back(v);
-        }
-    }
-    int H = 0;
-    for (int v : order) H = std::max(H, height[v]);
-    c->level_off.assign(H + 1, 0);
-    std::vector<int> count(H + 1, 0);
-    for (int v : order) count[height[v]]++;
-    // level h (1..H) stored at index h-1
-    c->level_off.assign(H + 1, 0);
-    for (int h = 1; h <= H; ++h) c->level_off[h] = c->level_off[h - 1] + count[h];
-    c->level_nodes.assign(N - 1, 0);
-    std::vector<int> fill(c->level_off.begin(), c->level_off.end() - 1);
-    // within a level: nodes with two internal children, then one, then none,
-    // each group by label.  Consecutive node slots share a wavefront, so the
-    // grouping keeps the tip and internal child paths of the kernels from
-    // both running in one wavefront for most of the level.
-    std::vector<int> sorted(order);
-    auto n_tip_children = [&](int v) { return (c->children[v].x < N) + (c->children[v].y < N); };
-    std::sort(sorted.begin(), sorted.end(), [&](int u, int v) {
-        const int cu = n_tip_children(u), cv = n_tip_children(v);
-        return cu != cv ? cu < cv : u < v;
-    });
-    for (int v : sorted) c->level_nodes[fill[height[v] - 1]++] = v;
-    c->height.swap(height);
-}
-
-// Traversal schedule of one upload: the level-synchronous part (the top:
-// every internal node outside the clades, grouped by height within the top)
-// and the clade walks, one list per slot count.
-struct Schedule {
-    std::vector<int> level_off;       // [H + 1] top levels
-    std::vector<int> level_nodes;     // top nodes by level
-    std::vector<int4> cl_post, cl_pre;
-    std::vector<int> cl_post_off, cl_pre_off;
-    int depth = 0;                    // stack blocks per slot
-};
-
-// LPT assignment of clades to ns slots (largest clade to the least loaded
-// slot); entries slot-major.
-void assign_clades(const std::vector<std::vector<int4>>& clades, int ns, std::vector<int4>& out,
-                   std::vector<int>& off) {
-    std::vector<int> order(clades.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int u, int v) { return clades[u].size() > clades[v].size(); });
-    std::vector<size_t> load(ns, 0);
-    std::vector<std::vector<int>> bins(ns);
-    for (int ci : order) {
-        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[b] += clades[ci].size();
-        bins[b].push_back(ci);
-    }
-    out.clear();
-    off.assign(ns + 1, 0);
-    for (int b = 0; b < ns; ++b) {
-        for (int ci : bins[b]) out.insert(out.end(), clades[ci].begin(), clades[ci].end());
-        off[b + 1] = (int)out.size();
-    }
-}
-
-// cap = 0: no clades (every internal node in the levels).
-void build_schedule(const pg_ctx* c, int cap, int ns_post, int ns_pre, Schedule& sc) {
-    const int N = c->n_tips, n_nodes = 2 * N - 1, root = n_nodes - 1;
-    const auto& ch = c->children;
-    // internal nodes in increasing height: children before parents
-    const std::vector<int>& up = c->level_nodes;
-    std::vector<int> sz(n_nodes, 0);  // internal nodes in the subtree
-    for (int v : up) sz[v] = 1 + sz[ch[v].x] + sz[ch[v].y];
-    // clade of each internal node (its clade root), -1 for the top
-    std::vector<int> clade(n_nodes, -1);
-    std::vector<int> roots;
-    for (auto it = up.rbegin(); it != up.rend(); ++it) {
-        const int v = *it;
-        if (v == root) continue;
-        const int p = c->parent[v];
-        if (clade[p] >= 0) {
-            clade[v] = clade[p];
-        } else if (sz[v] <= cap) {
-            clade[v] = v;
-            roots.push_back(v);
-        }
-    }
-    // top levels: height counted over top nodes only
-    std::vector<int> th(n_nodes, 0);
-    int H = 0;
-    for (int v : up) {
-        if (clade[v] >= 0) continue;
-        int h = 0;
-        for (int cc : {ch[v].x, ch[v].y})
-            if (cc >= N && clade[cc] < 0) h = std::max(h, th[cc]);
-        th[v] = h + 1;
-        H = std::max(H, th[v]);
-    }
-    std::vector<int> count(H + 1, 0), top;
-    for (int v : up)
-        if (clade[v] < 0) {
-            count[th[v]]++;
-            top.push_back(v);
-        }
-    sc.level_off.assign(H + 1, 0);
-    for (int h = 1; h <= H; ++h) sc.level_off[h] = sc.level_off[h - 1] + count[h];
-    // within a level: nodes with two internal children, then one, then none,
-    // each group by label.  Consecutive node slots share a wavefront, so the
-    // grouping keeps the tip and internal child paths of the kernels from
-    // both running in one wavefront for most of the level.
-    auto n_tip_children = [&](int v) { return (ch[v].x < N) + (ch[v].y < N); };
-    std::sort(top.begin(), top.end(), [&](int u, int v) {
-        const int cu = n_tip_children(u), cv = n_tip_children(v);
-        return cu != cv ? cu < cv : u < v;
-    });
-    sc.level_nodes.assign(top.size(), 0);
-    std::vector<int> fill(sc.level_off.begin(), sc.level_off.end() - 1);
-    for (int v : top) sc.level_nodes[fill[th[v] - 1]++] = v;
-    // clade entries in post order, the child with more internal nodes first
-    auto ordered = [&](int v) {
-        int f = ch[v].x, g = ch[v].y;
-        if (sz[g] > sz[f]) std::swap(f, g);
-        return std::make_pair(f, g);
-    };
-    std::sort(roots.begin(), roots.end());
-    std::vector<std::vector<int4>> lists;
-    sc.depth = 0;
-    for (int r : roots) {
-        std::vector<int4> e;
-        std::vector<std::pair<int, bool>> st{{r, false}};
-        while (!st.empty()) {
-            const auto [v, done] = st.back();
-            st.pop_back();
-            const auto [f, g] = ordered(v);
-            if (done) {
-                int flags = 0;
-                if (v == r) {
-                    flags = CL_ROOT;
-                } else {
-                    const auto [pf, pg2] = ordered(c->parent[v]);
-                    if (v == pf && pg2 >= N) flags = CL_STACK;
-                }
-                e.push_back(make_int4(v, f, g, flags));
-                continue;
-            }
-            st.push_back({v, true});
-            if (g >= N) st.push_back({g, false});
-            if (f >= N) st.push_back({f, false});
-        }
-        // stack depth of the walk (pops before pushes within an entry)
-        int sp = 0;
-        for (const int4& x : e) {
-            if (x.y >= N && x.z >= N) --sp;
-            if (x.w & CL_STACK) ++sp;
-            sc.depth = std::max(sc.depth, sp);
-        }
-        lists.push_back(std::move(e));
-    }
-    assign_clades(lists, ns_post, sc.cl_post, sc.cl_post_off);
-    assign_clades(lists, ns_pre, sc.cl_pre, sc.cl_pre_off);
-}
-
 int check_tree(pg_ctx* c, int32_t N, const int32_t* parent) {
     const int n_nodes = 2 * N - 1;
     const int root = n_nodes - 1;
     if (parent[root] != -1) return fail(c, PG_E_TREE, "parent[2N-2] must be -1 (root last)");
     std::vector<int> nchild(n_nodes, 0);
-    std::vector<int2> ch(n_nodes, make_int2(-1, -1));
+    std::vector<Kids> ch(n_nodes, Kids{-1, -1});
     for (int v = 0; v < root; ++v) {
         const int p = parent[v];
         if (p < N || p >= n_nodes)
@@ -426,238 +252,250 @@ int check_tree(pg_ctx* c, int32_t N, const int32_t* parent) {
     return PG_OK;
 }
 
-int upload(pg_ctx* c) {
+int check_ready(pg_ctx* c) {
     if (!c->tree_set || !c->patterns_set || !c->model_set)
         return fail(c, PG_E_STATE, "tree, patterns and model must all be set before evaluating");
     if (c->m_pat != c->m)
         return fail(c, PG_E_STATE, "patterns have " + std::to_string(c->m_pat) +
                                        " states but the model has " + std::to_string(c->m));
-    if (!c->dev_stale) return PG_OK;
-    PG_HIP(c, hipSetDevice(c->device));
-    const int N = c->n_tips, n_nodes = 2 * N - 1, B = n_nodes - 1;
-    const int M = c->m, K = c->K;
-    const size_t es = elem_size(c->precision);
+    return PG_OK;
+}
+
+// Host plan of the traversal (schedule, clade lists, top region); rebuilt
+// when the tree, patterns or model change.
+void ensure_plan(pg_ctx* c) {
+    if (!c->plan_stale) return;
     const bool split = c->precision == PG_SPLIT_BF16;
-    const int n_pb = c->S_pad / TP;
-    const int n_tiles = K * n_pb;
-    const size_t vec = (size_t)K * (split ? MP : M) * c->S_pad;
-    int r;
-    if ((r = ensure_buf(c, "t", sizeof(double) * B))) return r;
-    if ((r = ensure_buf(c, "P", split ? MF_SLOT_BYTES * (size_t)B * K : es * (size_t)B * K * M * M))) return r;
-    if (split) {
-        if ((r = ensure_buf(c, "eV", sizeof(double) * MP * MP))) return r;
-        if ((r = ensure_buf(c, "eVinv", sizeof(double) * MP * MP))) return r;
-        if ((r = ensure_buf(c, "eRe", sizeof(double) * MP))) return r;
-        if ((r = ensure_buf(c, "eIm", sizeof(double) * MP))) return r;
-        if ((r = ensure_buf(c, "eKind", sizeof(int) * MP))) return r;
-        if ((r = ensure_buf(c, "Qop", MF_QOP_BYTES))) return r;
-    }
-    if ((r = ensure_buf(c, "msg", es * vec * (N - 1)))) return r;
-    if ((r = ensure_buf(c, "qv", es * vec * (N - 1)))) return r;
-    if ((r = ensure_buf(c, "codes", (size_t)N * c->S_pad))) return r;
-    if ((r = ensure_buf(c, "masks", sizeof(unsigned long long) * 256))) return r;
-    // traversal schedule: clades for the small-M FP64 / FP32 kernels, with a
-    // smaller cap when a deep clade's stack would not fit CLADE_STACK_MAX
-    const int ns_post = split ? node_slots(M) : post_node_slots(M, c->precision);
-    const int ns_pre = split ? ns_post : pre_node_slots(M, c->precision);
-    // The clade cap is chosen per tree among a few sizes: larger clades mean
-    // fewer level-walk iterations above them (each ends at a barrier), but
-    // fewer clades to balance over the slots and deeper stacks.  Cost
-    // estimate: the busiest pre-order slot's clade entries plus twice the
-    // top's level iterations; caps whose stacks exceed CLADE_STACK_MAX are
-    // skipped.
-    Schedule sc;
-    if (!split && M * M <= TP) {
-        long best = -1;
-        for (int cap : {64, 48, 32, 24, 16}) {
-            if (cap > CLADE_CAP) continue;
-            Schedule t;
-            build_schedule(c, cap, ns_post, ns_pre, t);
-            if (es * std::max(ns_post, ns_pre) * t.depth * M * TP > (size_t)CLADE_STACK_MAX) continue;
-            long busiest = 0, top_iters = 0;
-            for (int b = 0; b < ns_pre; ++b) busiest = std::max<long>(busiest, t.cl_pre_off[b + 1] - t.cl_pre_off[b]);
-            for (size_t h = 0; h + 1 < t.level_off.size(); ++h)
-                top_iters += (t.level_off[h + 1] - t.level_off[h] + ns_pre - 1) / ns_pre;
-            const long cost = busiest + 2 * top_iters;
-            if (best < 0 || cost < best) {
-                best = cost;
-                sc = std::move(t);
-            }
-        }
-        if (best < 0) build_schedule(c, 0, ns_post, ns_pre, sc);
-    } else {
-        build_schedule(c, 0, ns_post, ns_pre, sc);
-    }
-    const int n_top = (int)sc.level_nodes.size(), n_cl = (int)sc.cl_post.size();
-    const bool one_list = ns_post == ns_pre;
-    const size_t n_entries = (size_t)n_top + n_cl * (one_list ? 1 : 2);
-    if ((r = ensure_buf(c, "level_off", sizeof(int) * sc.level_off.size()))) return r;
-    if ((r = ensure_buf(c, "sched", sizeof(int4) * n_entries))) return r;
-    if ((r = ensure_buf(c, "cl_off", sizeof(int) * (ns_post + ns_pre + 2)))) return r;
-    if ((r = ensure_buf(c, "Q64", sizeof(double) * M * M))) return r;
-    if ((r = ensure_buf(c, "Q2_64", sizeof(double) * M * M))) return r;
-    if ((r = ensure_buf(c, "pi64", sizeof(double) * M))) return r;
-    if ((r = ensure_buf(c, "rates", sizeof(double) * K))) return r;
-    if ((r = ensure_buf(c, "catw", sizeof(double) * K))) return r;
-    if ((r = ensure_buf(c, "weights", sizeof(double) * c->S_pad))) return r;
-    if ((r = ensure_buf(c, "rootL", sizeof(double) * K * c->S_pad))) return r;
-    if ((r = ensure_buf(c, "rootE", sizeof(int) * K * c->S_pad))) return r;
-    if ((r = ensure_buf(c, "partial", sizeof(double) * (size_t)n_tiles * B))) return r;
-    if ((r = ensure_buf(c, "partial2", sizeof(double) * (size_t)n_tiles * B))) return r;
-    if ((r = ensure_buf(c, "logl_part", sizeof(double) * (size_t)n_pb))) return r;
-    if ((r = ensure_buf(c, "flag_part", sizeof(int) * (size_t)n_pb))) return r;
-    if ((r = ensure_buf(c, "grad", sizeof(double) * B))) return r;
-    if ((r = ensure_buf(c, "hess", sizeof(double) * B))) return r;
-    if ((r = ensure_buf(c, "logL", sizeof(double) * 2))) return r;
-    if ((r = ensure_buf(c, "status", sizeof(int) * 2))) return r;
-    if (c->bm_n > 0) {
-        if ((r = ensure_buf(c, "bm_Q", sizeof(double) * c->bm_Q.size()))) return r;
-        if ((r = ensure_buf(c, "bm_Q2", sizeof(double) * c->bm_Q2.size()))) return r;
-        if ((r = ensure_buf(c, "bm_qnorm", sizeof(double) * c->bm_qnorm.size()))) return r;
-        if ((r = ensure_buf(c, "bm_model", sizeof(int) * c->bm_model.size()))) return r;
-    }
+    PlanParams p;
+    p.n_states = c->m;
+    p.elem_bytes = (int)elem_size(c->precision);
+    p.clades = !split && c->m * c->m <= TP;
+    p.top_region = !split;
+    p.ns_post = split ? node_slots(c->m) : post_node_slots(c->m, c->precision);
+    p.ns_pre = split ? p.ns_post : pre_node_slots(c->m, c->precision);
+    TraversalPlan plan;
+    plan_traversal(c->n_tips, c->parent.data(), c->children.data(), c->lv, p, plan);
+    c->plan = std::move(plan);
+    c->plan_stale = false;
+}
 
-    hipStream_t st = c->stream;
-    auto put = [&](const char* name, const void* src, size_t bytes) {
-        return hipMemcpyAsync(c->bufs[name].ptr, src, bytes, hipMemcpyHostToDevice, st);
-    };
-    // pre-order top region: levels from the root down while every level has
-    // at most TOP_LEVEL_MAX_NODES nodes and their q vectors fit TOP_LDS_MAX
-    const int H = (int)sc.level_off.size() - 1;
-    const int top_cap = std::min<int>(255, TOP_LDS_MAX / (int)(es * M * TP));
-    int top_level = H, top_nodes = 0;
-    for (int h = H - 1; h >= 0 && !split; --h) {
-        const int n_h = sc.level_off[h + 1] - sc.level_off[h];
-        if (n_h > TOP_LEVEL_MAX_NODES || top_nodes + n_h > top_cap) break;
-        top_nodes += n_h;
-        top_level = h;
-    }
-    std::vector<int> region(n_nodes, 0);
-    {
-        int next = 1;
-        for (int i = sc.level_off[top_level]; i < sc.level_off[H]; ++i) region[sc.level_nodes[i]] = next++;
-    }
-    // [top entries][post clade list][pre clade list unless the same]
-    std::vector<int4> sched(n_entries);
-    for (int i = 0; i < n_top; ++i) {
-        const int k = sc.level_nodes[i];
-        // a node with one tip child lists its internal child first, so the
-        // first child of every such node takes the same path
-        int c0 = c->children[k].x, c1 = c->children[k].y;
-        if (c0 < N && c1 >= N) std::swap(c0, c1);
-        sched[i] = make_int4(k, c0, c1, region[k] | (region[c0] << 8) | (region[c1] << 16));
-    }
-    std::copy(sc.cl_post.begin(), sc.cl_post.end(), sched.begin() + n_top);
-    if (!one_list) std::copy(sc.cl_pre.begin(), sc.cl_pre.end(), sched.begin() + n_top + n_cl);
-    std::vector<int> cl_off(sc.cl_post_off);
-    cl_off.insert(cl_off.end(), sc.cl_pre_off.begin(), sc.cl_pre_off.end());
-    PG_HIP(c, put("codes", c->codes.data(), c->codes.size()));
-    PG_HIP(c, put("masks", c->masks.data(), sizeof(unsigned long long) * 256));
-    PG_HIP(c, put("level_off", sc.level_off.data(), sizeof(int) * sc.level_off.size()));
-    PG_HIP(c, put("sched", sched.data(), sizeof(int4) * sched.size()));
-    PG_HIP(c, put("cl_off", cl_off.data(), sizeof(int) * cl_off.size()));
-    PG_HIP(c, put("Q64", c->Q.data(), sizeof(double) * M * M));
-    PG_HIP(c, put("Q2_64", c->Q2.data(), sizeof(double) * M * M));
-    PG_HIP(c, put("pi64", c->pi.data(), sizeof(double) * M));
-    PG_HIP(c, put("rates", c->rates.data(), sizeof(double) * K));
-    PG_HIP(c, put("catw", c->catw.data(), sizeof(double) * K));
-    PG_HIP(c, put("weights", c->weights.data(), sizeof(double) * c->S_pad));
-    if (c->bm_n > 0) {
-        PG_HIP(c, put("bm_Q", c->bm_Q.data(), sizeof(double) * c->bm_Q.size()));
-        PG_HIP(c, put("bm_Q2", c->bm_Q2.data(), sizeof(double) * c->bm_Q2.size()));
-        PG_HIP(c, put("bm_qnorm", c->bm_qnorm.data(), sizeof(double) * c->bm_qnorm.size()));
-        PG_HIP(c, put("bm_model", c->bm_model.data(), sizeof(int) * c->bm_model.size()));
-    }
-    if (split) {
-        PG_HIP(c, put("eV", c->eV.data(), sizeof(double) * MP * MP));
-        PG_HIP(c, put("eVinv", c->eVinv.data(), sizeof(double) * MP * MP));
-        PG_HIP(c, put("eRe", c->eRe.data(), sizeof(double) * MP));
-        PG_HIP(c, put("eIm", c->eIm.data(), sizeof(double) * MP));
-        PG_HIP(c, put("eKind", c->eKind.data(), sizeof(int) * MP));
-        PG_HIP(c, put("Qop", c->Qop.data(), MF_QOP_BYTES));
-    }
-    // pageable host sources: make sure the copies are done before the vectors move
-    PG_HIP(c, hipStreamSynchronize(st));
+// Sizes of the device buffers of one evaluation.
+struct Dims {
+    int64_t N = 0, S_pad = 0, M = 0, K = 0;
+    int precision = PG_FP64;
+    int64_t n_entries = 0, n_level_off = 0, n_cl_off = 0;  // schedule
+    int64_t bm_n = 0;                                      // per-branch models
+    bool updates = false;                                  // per-node exponents kept
+};
 
-    EvalArgs& a = c->args;
+struct BufSpec {
+    const char* name;
+    size_t bytes;
+    const void* src = nullptr;  // host data (bytes) to upload, or NULL
+};
+
+// Every device buffer of an evaluation.  `lean` leaves out what the
+// allocation-free entry point does not use (its caller's t, logL and grad,
+// the Hessian's tile sums, the per-node exponents).
+std::vector<BufSpec> buffer_specs(const Dims& d, bool lean) {
+    const bool split = d.precision == PG_SPLIT_BF16;
+    const size_t es = elem_size(d.precision);
+    const size_t N = d.N, B = 2 * d.N - 2, M = d.M, K = d.K, S_pad = d.S_pad;
+    const size_t n_pb = S_pad / TP, n_tiles = K * n_pb;
+    const size_t vec = K * (split ? MP : M) * S_pad;
+    std::vector<BufSpec> v;
+    auto add = [&](const char* name, size_t bytes) { v.push_back(BufSpec{name, bytes}); };
+    if (!lean) add("t", sizeof(double) * B);
+    add("P", split ? MF_SLOT_BYTES * B * K : es * B * K * M * M);
+    if (split) {
+        add("eV", sizeof(double) * MP * MP);
+        add("eVinv", sizeof(double) * MP * MP);
+        add("eRe", sizeof(double) * MP);
+        add("eIm", sizeof(double) * MP);
+        add("eKind", sizeof(int) * MP);
+        add("Qop", MF_QOP_BYTES);
+    }
+    add("msg", es * vec * (N - 1));
+    add("qv", es * vec * (N - 1));
+    add("codes", N * S_pad);
+    add("masks", sizeof(unsigned long long) * 256);
+    add("level_off", sizeof(int) * d.n_level_off);
+    add("sched", sizeof(int4) * d.n_entries);
+    add("cl_off", sizeof(int) * d.n_cl_off);
+    add("Q64", sizeof(double) * M * M);
+    add("Q2_64", sizeof(double) * M * M);
+    add("pi64", sizeof(double) * M);
+    add("rates", sizeof(double) * K);
+    add("catw", sizeof(double) * K);
+    add("weights", sizeof(double) * S_pad);
+    add("rootL", sizeof(double) * K * S_pad);
+    add("rootE", sizeof(int) * K * S_pad);
+    add("partial", sizeof(double) * n_tiles * B);
+    if (!lean) add("partial2", sizeof(double) * n_tiles * B);
+    add("logl_part", sizeof(double) * n_pb);
+    add("flag_part", sizeof(int) * n_pb);
+    if (!lean) {
+        add("grad", sizeof(double) * B);
+        add("hess", sizeof(double) * B);
+        add("logL", sizeof(double) * 2);
+    }
+    add("status", sizeof(int) * 2);
+    if (d.bm_n > 0) {
+        add("bm_Q", sizeof(double) * d.bm_n * M * M);
+        add("bm_Q2", sizeof(double) * d.bm_n * M * M);
+        add("bm_qnorm", sizeof(double) * d.bm_n);
+        add("bm_model", sizeof(int) * B);
+    }
+    if (d.updates && !lean) add("expo", sizeof(int16_t) * (N - 1) * n_tiles * TP);
+    return v;
+}
+
+Dims ctx_dims(const pg_ctx* c) {
+    Dims d;
+    d.N = c->n_tips;
+    d.S_pad = c->S_pad;
+    d.M = c->m;
+    d.K = c->K;
+    d.precision = c->precision;
+    d.n_entries = (int64_t)c->plan.sched.size();
+    d.n_level_off = (int64_t)c->plan.level_off.size();
+    d.n_cl_off = (int64_t)c->plan.cl_off.size();
+    d.bm_n = c->bm_n;
+    d.updates = c->updates;
+    return d;
+}
+
+// The host data each input buffer is uploaded from.
+void attach_sources(const pg_ctx* c, std::vector<BufSpec>& specs) {
+    static_assert(sizeof(Ent) == sizeof(int4), "schedule entries are uploaded as int4");
+    const std::map<std::string, const void*> src = {
+        {"eV", c->eV.data()}, {"eVinv", c->eVinv.data()}, {"eRe", c->eRe.data()}, {"eIm", c->eIm.data()},
+        {"eKind", c->eKind.data()}, {"Qop", c->Qop.data()}, {"codes", c->codes.data()},
+        {"masks", c->masks.data()}, {"level_off", c->plan.level_off.data()}, {"sched", c->plan.sched.data()},
+        {"cl_off", c->plan.cl_off.data()}, {"Q64", c->Q.data()}, {"Q2_64", c->Q2.data()},
+        {"pi64", c->pi.data()}, {"rates", c->rates.data()}, {"catw", c->catw.data()},
+        {"weights", c->weights.data()}, {"bm_Q", c->bm_Q.data()}, {"bm_Q2", c->bm_Q2.data()},
+        {"bm_qnorm", c->bm_qnorm.data()}, {"bm_model", c->bm_model.data()}};
+    for (BufSpec& s : specs) {
+        auto it = src.find(s.name);
+        if (it != src.end()) s.src = it->second;
+    }
+}
+
+// EvalArgs of the context's plan with buffers at at(name) (NULL for a
+// buffer that is not there).
+template <typename At>
+void fill_args(const pg_ctx* c, At&& at, EvalArgs& a) {
+    const TraversalPlan& pl = c->plan;
+    const int N = c->n_tips, n_nodes = 2 * N - 1, M = c->m;
+    const bool split = c->precision == PG_SPLIT_BF16;
     a = EvalArgs{};
     a.n_tips = N;
     a.n_nodes = n_nodes;
-    a.n_branches = B;
+    a.n_branches = n_nodes - 1;
     a.root = n_nodes - 1;
-    a.K = K;
+    a.K = c->K;
     a.M = M;
     a.S = c->S;
     a.S_pad = c->S_pad;
-    a.n_pb = n_pb;
-    a.n_tiles = n_tiles;
-    a.n_levels = H;
+    a.n_pb = c->S_pad / TP;
+    a.n_tiles = c->K * a.n_pb;
+    a.n_levels = pl.n_levels();
     a.qnorm = c->qnorm;
     for (int e = 0; e < 16; ++e) a.Qs[e] = (e < M * M) ? c->Q[e] : 0.0;
     for (int e = 0; e < 16; ++e) a.Q2s[e] = (e < M * M) ? c->Q2[e] : 0.0;
     for (int e = 0; e < 4; ++e) a.pis[e] = (e < M) ? c->pi[e] : 0.0;
-    a.t = buf<double>(c, "t");
-    a.P = c->bufs["P"].ptr;
-    a.msg = c->bufs["msg"].ptr;
-    a.qv = c->bufs["qv"].ptr;
-    a.codes = buf<uint8_t>(c, "codes");
-    a.masks = buf<unsigned long long>(c, "masks");
-    a.level_off = buf<int>(c, "level_off");
-    a.sched = buf<int4>(c, "sched");
-    a.top_level = top_level;
-    a.top_nodes = top_nodes;
-    a.n_sched = n_top;
-    if (n_cl > 0) {
-        a.n_cl = n_cl;
-        a.cl_depth = sc.depth;
-        a.cl_post = a.sched + n_top;
-        a.cl_pre = one_list ? a.cl_post : a.cl_post + n_cl;
-        a.cl_post_off = buf<int>(c, "cl_off");
-        a.cl_pre_off = a.cl_post_off + ns_post + 1;
+    a.t = static_cast<const double*>(at("t"));
+    a.P = at("P");
+    a.msg = at("msg");
+    a.qv = at("qv");
+    a.codes = static_cast<const uint8_t*>(at("codes"));
+    a.masks = static_cast<const unsigned long long*>(at("masks"));
+    a.level_off = static_cast<const int*>(at("level_off"));
+    a.sched = static_cast<const int4*>(at("sched"));
+    a.top_level = pl.top_level;
+    a.top_nodes = pl.top_nodes;
+    a.n_sched = pl.n_top;
+    if (pl.n_cl > 0) {
+        a.n_cl = pl.n_cl;
+        a.cl_depth = pl.depth;
+        a.cl_post = a.sched + pl.n_top;
+        a.cl_pre = pl.one_list ? a.cl_post : a.cl_post + pl.n_cl;
+        a.cl_post_off = static_cast<const int*>(at("cl_off"));
+        a.cl_pre_off = a.cl_post_off + pl.ns_post + 1;
     }
     // stage the schedule in LDS when it fits and leaves each kernel's total
     // within LDS_BLOCK_MAX
-    a.sched_lds = (sizeof(int4) * (size_t)(n_top + n_cl) <= (size_t)SCHED_LDS_MAX) ? 1 : 0;
+    a.sched_lds = (sizeof(int4) * (size_t)(pl.n_top + pl.n_cl) <= (size_t)SCHED_LDS_MAX) ? 1 : 0;
     if (!split && (post_lds_bytes(a, c->precision) > (size_t)LDS_BLOCK_MAX ||
                    pre_lds_bytes(a, c->precision) > (size_t)LDS_BLOCK_MAX))
         a.sched_lds = 0;
-    a.Q64 = buf<double>(c, "Q64");
-    a.Q2_64 = buf<double>(c, "Q2_64");
-    a.pi64 = buf<double>(c, "pi64");
-    a.rates = buf<double>(c, "rates");
-    a.catw = buf<double>(c, "catw");
-    a.weights = buf<double>(c, "weights");
-    a.rootL = buf<double>(c, "rootL");
-    a.rootE = buf<int>(c, "rootE");
-    a.partial = buf<double>(c, "partial");
-    a.partial2 = buf<double>(c, "partial2");
+    a.Q64 = static_cast<const double*>(at("Q64"));
+    a.Q2_64 = static_cast<const double*>(at("Q2_64"));
+    a.pi64 = static_cast<const double*>(at("pi64"));
+    a.rates = static_cast<const double*>(at("rates"));
+    a.catw = static_cast<const double*>(at("catw"));
+    a.weights = static_cast<const double*>(at("weights"));
+    a.rootL = static_cast<double*>(at("rootL"));
+    a.rootE = static_cast<int*>(at("rootE"));
+    a.partial = static_cast<double*>(at("partial"));
+    a.partial2 = static_cast<double*>(at("partial2"));
     a.r1 = nullptr;  // allocated by the first Hessian call
-    a.logl_part = buf<double>(c, "logl_part");
-    a.flag_part = buf<int>(c, "flag_part");
-    a.grad_out = buf<double>(c, "grad");
-    a.hess_out = buf<double>(c, "hess");
-    a.logL_out = buf<double>(c, "logL");
-    a.status = buf<int>(c, "status");
+    a.logl_part = static_cast<double*>(at("logl_part"));
+    a.flag_part = static_cast<int*>(at("flag_part"));
+    a.grad_out = static_cast<double*>(at("grad"));
+    a.hess_out = static_cast<double*>(at("hess"));
+    a.logL_out = static_cast<double*>(at("logL"));
+    a.status = static_cast<int*>(at("status"));
+    a.expo = static_cast<int16_t*>(at("expo"));
     a.n_models = c->bm_n;
-    if (c->updates) {
-        if ((r = ensure_buf(c, "expo", sizeof(int16_t) * (size_t)(N - 1) * n_tiles * TP))) return r;
-        a.expo = buf<int16_t>(c, "expo");
-    }
     if (c->bm_n > 0) {
-        a.Qm = buf<double>(c, "bm_Q");
-        a.Q2m = buf<double>(c, "bm_Q2");
-        a.qnorm_m = buf<double>(c, "bm_qnorm");
-        a.branch_model = buf<int>(c, "bm_model");
+        a.Qm = static_cast<const double*>(at("bm_Q"));
+        a.Q2m = static_cast<const double*>(at("bm_Q2"));
+        a.qnorm_m = static_cast<const double*>(at("bm_qnorm"));
+        a.branch_model = static_cast<const int*>(at("bm_model"));
     }
     if (split) {
-        a.eV = buf<double>(c, "eV");
-        a.eVinv = buf<double>(c, "eVinv");
-        a.eRe = buf<double>(c, "eRe");
-        a.eIm = buf<double>(c, "eIm");
-        a.eKind = buf<int>(c, "eKind");
-        a.Qop = c->bufs["Qop"].ptr;
+        a.eV = static_cast<const double*>(at("eV"));
+        a.eVinv = static_cast<const double*>(at("eVinv"));
+        a.eRe = static_cast<const double*>(at("eRe"));
+        a.eIm = static_cast<const double*>(at("eIm"));
+        a.eKind = static_cast<const int*>(at("eKind"));
+        a.Qop = at("Qop");
         a.expm_taylor = c->expm_taylor ? 1 : 0;
     }
+}
+
+// Copies made from the context's pageable host vectors by the
+// allocation-free entry point may still be in flight: wait for them before
+// those vectors change.
+int settle_host_copies(pg_ctx* c) {
+    if (!c->host_copies) return PG_OK;
+    PG_HIP(c, hipStreamSynchronize(c->stream));
+    c->host_copies = false;
+    return PG_OK;
+}
+
+// Allocate (or keep) the context's device buffers and upload its inputs.
+int upload(pg_ctx* c) {
+    int r = check_ready(c);
+    if (r) return r;
+    if (!c->dev_stale) return PG_OK;
+    PG_HIP(c, hipSetDevice(c->device));
+    if ((r = settle_host_copies(c))) return r;
+    ensure_plan(c);
+    std::vector<BufSpec> specs = buffer_specs(ctx_dims(c), false);
+    attach_sources(c, specs);
+    for (const BufSpec& s : specs)
+        if ((r = ensure_buf(c, s.name, s.bytes))) return r;
+    for (const BufSpec& s : specs)
+        if (s.src) PG_HIP(c, hipMemcpyAsync(c->bufs[s.name].ptr, s.src, s.bytes, hipMemcpyHostToDevice, c->stream));
+    // pageable host sources: make sure the copies are done before the vectors move
+    PG_HIP(c, hipStreamSynchronize(c->stream));
+    fill_args(c, [&](const char* name) -> void* {
+        auto it = c->bufs.find(name);
+        return it == c->bufs.end() ? nullptr : it->second.ptr;
+    }, c->args);
     c->dev_stale = false;
     c->have_partials = false;
     return PG_OK;
@@ -773,11 +611,31 @@ int guarded(pg_ctx* c, F&& body) {
 
 namespace pg {
 
-// Device state of a context for the serving scheduler: allocate and upload
-// if needed (blocking), then hand out its EvalArgs.
-int ctx_prepare(pg_ctx* c) {
+// Device state of a context for the serving scheduler: the host plan (on
+// the thread that opens a session), the bytes it will take, and the upload
+// (allocate and copy on `stream`, blocking) before its EvalArgs are handed out.
+int ctx_plan(pg_ctx* c) {
     return guarded(c, [&] {
+        int r = check_ready(c);
+        if (r == PG_OK) ensure_plan(c);
+        return r;
+    });
+}
+
+int64_t ctx_need_bytes(pg_ctx* c, size_t granule) {
+    ensure_plan(c);
+    int64_t tot = 0;
+    for (const BufSpec& s : buffer_specs(ctx_dims(c), false))
+        tot += (int64_t)((std::max<size_t>(s.bytes, 256) + granule - 1) / granule * granule);
+    return tot;
+}
+
+int ctx_prepare(pg_ctx* c, hipStream_t stream) {
+    return guarded(c, [&] {
+        hipStream_t own = c->stream;
+        c->stream = stream;
         int r = upload(c);
+        c->stream = own;
         if (r == PG_OK) c->have_partials = false;
         return r;
     });
@@ -882,17 +740,19 @@ int pg_set_tree(pg_ctx* c, int32_t N, const int32_t* parent) {
     if (!parent) return fail(c, PG_E_INVALID, "parent is NULL");
     if (N < 2 || N > (1 << 26)) return fail(c, PG_E_INVALID, "need 2 <= n_tips <= 2^26");
     return guarded(c, [&] {
-        int r = check_tree(c, N, parent);
+        int r = settle_host_copies(c);
         if (r) return r;
+        if ((r = check_tree(c, N, parent))) return r;
         if (c->n_tips != N) {
             c->patterns_set = false;
             c->bm_n = 0;  // branch models are per branch of the old tree
         }
         c->n_tips = N;
         c->parent.assign(parent, parent + 2 * N - 1);
-        build_levels(c);
+        build_levels(N, c->children.data(), c->lv);
         c->tree_set = true;
         c->dev_stale = true;
+        c->plan_stale = true;
         c->have_partials = false;
         return PG_OK;
     });
@@ -905,6 +765,7 @@ int pg_set_patterns(pg_ctx* c, int32_t S, int32_t m, const uint64_t* tip_masks, 
     if (S < 1) return fail(c, PG_E_INVALID, "need n_patterns >= 1");
     if (m < 2 || m > 64) return fail(c, PG_E_PATTERNS, "need 2 <= n_states <= 64");
     return guarded(c, [&] {
+        if (int r0 = settle_host_copies(c)) return r0;
         const int N = c->n_tips;
         const int S_pad = (S + TP - 1) / TP * TP;
         const unsigned long long full = (m == 64) ? ~0ull : ((1ull << m) - 1);
@@ -968,6 +829,7 @@ int pg_set_model(pg_ctx* c, int32_t m, const double* Q, const double* pi, int32_
     if (!kernel_supported(m, c->precision))
         return fail(c, PG_E_UNSUPPORTED, "no kernel compiled for " + std::to_string(m) + " states");
     return guarded(c, [&] {
+        if (int r0 = settle_host_copies(c)) return r0;
         double amax = 1.0;
         for (int i = 0; i < m * m; ++i) {
             if (!std::isfinite(Q[i])) return fail(c, PG_E_MODEL, "Q has a non-finite entry");
@@ -1018,6 +880,7 @@ int pg_set_model(pg_ctx* c, int32_t m, const double* Q, const double* pi, int32_
         if (old_m != m) c->bm_n = 0;  // branch models have the old state count
         c->model_set = true;
         c->dev_stale = true;
+        c->plan_stale = true;
         c->have_partials = false;
         return PG_OK;
     });
@@ -1031,6 +894,7 @@ int pg_set_branch_models(pg_ctx* c, int32_t n_models, const double* Q, const int
     if (n_models > 0 && c->precision == PG_SPLIT_BF16)
         return fail(c, PG_E_UNSUPPORTED, "per-branch rate matrices have no split-BF16 kernel");
     return guarded(c, [&] {
+        if (int r0 = settle_host_copies(c)) return r0;
         const int m = c->m, B = 2 * c->n_tips - 2;
         std::vector<double> Qs, Q2s, qn;
         std::vector<int> model;
@@ -1116,23 +980,12 @@ int pg_logL_update(pg_ctx* c, int32_t n, const int32_t* branches, const double* 
         } else {
             // dirty nodes: each changed internal node (its message changes
             // with its matrix) and every ancestor of a changed branch
-            std::vector<char> dirty(2 * N - 1, 0);
-            std::vector<int> list;
-            for (int i = 0; i < n; ++i) {
-                const int b = branches[i];
-                if (std::find(list.begin(), list.end(), b) == list.end()) list.push_back(b);
-                for (int v = (b >= N) ? b : c->parent[b]; v >= 0 && !dirty[v]; v = c->parent[v]) dirty[v] = 1;
-            }
-            const int H = (int)c->level_off.size() - 1;
-            std::vector<int> off(H + 1, 0);
-            std::vector<int4> sched;
-            for (int h = 0; h < H; ++h) {
-                for (int i = c->level_off[h]; i < c->level_off[h + 1]; ++i) {
-                    const int k = c->level_nodes[i];
-                    if (dirty[k]) sched.push_back(make_int4(k, c->children[k].x, c->children[k].y, 0));
-                }
-                off[h + 1] = (int)sched.size();
-            }
+            UpdatePlan up;
+            plan_update(N, c->parent.data(), c->children.data(), c->lv, n, branches, up);
+            const std::vector<int>& list = up.list;
+            const std::vector<Ent>& sched = up.sched;
+            const std::vector<int>& off = up.level_off;
+            const int H = (int)off.size() - 1;
             // one pinned staging area and one copy: [t][branch list][schedule][level offsets]
             const size_t o_list = sizeof(double) * B;
             const size_t o_sched = (o_list + sizeof(int) * B + 15) & ~size_t(15);
@@ -1154,7 +1007,7 @@ int pg_logL_update(pg_ctx* c, int32_t n, const int32_t* branches, const double* 
             char* hs = static_cast<char*>(c->u_pinned);
             std::memcpy(hs, t.data(), sizeof(double) * B);
             std::memcpy(hs + o_list, list.data(), sizeof(int) * list.size());
-            std::memcpy(hs + o_sched, sched.data(), sizeof(int4) * sched.size());
+            std::memcpy(hs + o_sched, sched.data(), sizeof(Ent) * sched.size());
             std::memcpy(hs + o_level, off.data(), sizeof(int) * off.size());
             char* ds = static_cast<char*>(c->bufs["u_stage"].ptr);
             c->have_partials = false;
@@ -1354,19 +1207,20 @@ int64_t pg_device_bytes(const pg_ctx* c) {
 
 int64_t pg_footprint_bytes(int32_t N, int32_t S, int32_t m, int32_t K, int precision) {
     if (N < 2 || S < 1 || m < 2 || K < 1) return -1;
-    const bool split = precision == PG_SPLIT_BF16;
-    const int64_t es = precision == PG_FP64 ? 8 : 4;
-    const int64_t S_pad = (S + TP - 1) / TP * TP;
-    const int64_t B = 2 * (int64_t)N - 2;
-    const int64_t n_tiles = K * (S_pad / TP);
-    const int64_t ms = split ? MP : m;
+    // the buffers an evaluation allocates, with the schedule at its largest
+    // (top entries plus two clade lists: at most 2 (N - 1) entries, N level
+    // offsets, two slot-range tables); each allocation is at least 256 B
+    Dims d;
+    d.N = N;
+    d.S_pad = ((int64_t)S + TP - 1) / TP * TP;
+    d.M = m;
+    d.K = K;
+    d.precision = precision;
+    d.n_entries = 2 * ((int64_t)N - 1);
+    d.n_level_off = N;
+    d.n_cl_off = 2 * (node_slots(2) + 1);
     int64_t tot = 0;
-    tot += 2 * es * (int64_t)K * ms * S_pad * (N - 1);      // msg + qv
-    tot += split ? (int64_t)MF_SLOT_BYTES * B * K : es * B * K * m * m;  // P
-    tot += (int64_t)N * S_pad;                             // codes
-    tot += 8 * (n_tiles * B + (S_pad / TP) * B);           // tile partial sums
-    tot += (8 + 8 + 4) * (int64_t)K * S_pad + 8 * S_pad;   // root values, rho, weights
-    tot += 8 * 4 * B + 4 * 3 * (int64_t)N + 4096;          // t, grad, hess, schedule
+    for (const BufSpec& sp : buffer_specs(d, false)) tot += (int64_t)std::max<size_t>(sp.bytes, 256);
     return tot;
 }
 

@@ -9,24 +9,15 @@
 #include <vector>
 
 #include "../../include/phylograd.h"
+#include "plan.h"
 
 namespace pg {
 
-// Patterns per tile: one tile is TP consecutive patterns of one rate
-// category.  A node's data for one tile, M states x TP patterns, is one
-// contiguous run (512 B for FP64 and M = 4).
-constexpr int TP = 16;
 // Node slots per workgroup of the traversal kernels (each slot is TP lanes):
 // the workgroup has node_slots(M) * TP threads.
 __host__ __device__ constexpr int node_slots(int M) { return M <= 8 ? 32 : 16; }
 // Branches per block of the gradient reduction.
 constexpr int GS_BRANCHES = 16;
-// The schedule is staged in LDS when it fits this budget (bytes).
-constexpr int SCHED_LDS_MAX = 32768;
-// LDS budget for the pre-order top region's q vectors, and the largest
-// level it admits (one node per node slot).
-constexpr int TOP_LDS_MAX = 32768;
-constexpr int TOP_LEVEL_MAX_NODES = 16;
 // Node slots of the pre-order kernel (FP64 small M: fewer, heavier slots).
 #ifndef PG_PRE_NS64
 #define PG_PRE_NS64 16
@@ -55,25 +46,6 @@ __host__ __device__ constexpr int post_slots(int M) {
 inline int post_node_slots(int M, int precision) {
     return precision == PG_FP32 ? post_slots<float>(M) : post_slots<double>(M);
 }
-// Clades (small M, FP64 and FP32): the maximal subtrees below the root with
-// at most a cap of internal nodes (chosen per tree, at most CLADE_CAP) are
-// walked depth first, each by one node slot, with a per-slot LDS stack; the
-// other internal nodes (the top) keep the level-synchronous walk.  Entry
-// flags of a clade walk:
-#ifndef PG_CLADE_CAP
-#define PG_CLADE_CAP 64
-#endif
-constexpr int CLADE_CAP = PG_CLADE_CAP;
-constexpr int CL_STACK = 1;  // post: push the node's message; pre: pop its q
-constexpr int CL_ROOT = 2;   // clade root: pre reads its q from memory
-// LDS budget of the clade stacks of one workgroup, and of a traversal
-// workgroup's dynamic LDS in all (the schedule is left in memory beyond it).
-#ifndef PG_CLADE_STACK_MAX
-#define PG_CLADE_STACK_MAX 32768
-#endif
-constexpr int CLADE_STACK_MAX = PG_CLADE_STACK_MAX;
-constexpr int LDS_BLOCK_MAX = 61440;
-
 __host__ __device__ inline int gsum_blocks(int n_branches) {
     return (n_branches + GS_BRANCHES - 1) / GS_BRANCHES;
 }
@@ -215,8 +187,10 @@ struct EigenSystem {
 bool eigen_decompose(int m, const double* Q, EigenSystem& es);
 
 // Device memory source of a context (the serving scheduler's pool).
+// acquire returns a block of at least `bytes` (its size in *granted), or
+// NULL; both calls may come from different threads.
 struct DeviceAllocator {
-    virtual void* acquire(size_t bytes) = 0;
+    virtual void* acquire(size_t bytes, size_t* granted) = 0;
     virtual void release(void* p, size_t bytes) = 0;
     virtual ~DeviceAllocator() = default;
 };
@@ -226,7 +200,14 @@ struct DeviceAllocator {
 struct pg_ctx;
 namespace pg {
 pg_ctx* ctx_new_session(int device, int precision, hipStream_t stream, DeviceAllocator* alloc);
-int ctx_prepare(pg_ctx* c);
+// Host planning of the device state (no device work).
+int ctx_plan(pg_ctx* c);
+// Device bytes the context's buffers take when each allocation is rounded
+// up to a multiple of `granule`.
+int64_t ctx_need_bytes(pg_ctx* c, size_t granule);
+// Allocate and upload on `stream` (waits for it), then keep using the
+// context's own stream.
+int ctx_prepare(pg_ctx* c, hipStream_t stream);
 EvalArgs ctx_args(const pg_ctx* c);
 int ctx_precision(const pg_ctx* c);
 const char* ctx_error(const pg_ctx* c);

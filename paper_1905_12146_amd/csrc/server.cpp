@@ -1,10 +1,13 @@
 // Serving scheduler: many independent gradient sessions on one GPU with
 // admission by HBM footprint and continuous batching.
 //
-// A session owns a context (tree, patterns, model, resident partials).  A
-// session is admitted when the device bytes it needs fit the budget next to
-// the admitted sessions and a session slot is free; otherwise it waits in
-// arrival order.  The worker thread repeatedly takes, from every admitted
+// A session owns a context (tree, patterns, model, resident partials); its
+// host-side planning runs on the thread that opens it.  A session is
+// admitted when the device bytes it needs fit the budget next to the
+// admitted sessions and a session slot is free; otherwise it waits in
+// arrival order.  Admission hands the session to an upload thread, which
+// allocates its buffers and copies its inputs on a stream of its own while
+// the worker keeps running batches.  The worker thread repeatedly takes, from every admitted
 // session with a pending call, its oldest call and runs all of them as one
 // batch: one launch each of the transition-matrix, post-order, pre-order and
 // reduction kernels, whose blocks are mapped to (call, block-of-that-call).
@@ -50,52 +53,71 @@ struct Call {
 
 struct Session {
     pg_ctx* ctx = nullptr;
-    int64_t footprint = 0;
+    int64_t reserve = 0;   // bytes reserved for it at admission (pool granularity)
+    int64_t charged = 0;   // bytes charged to the budget while admitted
     int n_branches = 0;
     int M = 0;
-    bool admitted = false;
+    enum State { WAITING, UPLOADING, ADMITTED } state = WAITING;
     bool closing = false;
     std::deque<int64_t> pending;
 };
 
 // Device memory pool: freed session buffers are kept and handed to later
-// sessions (best fit within 2x), so admission and closing avoid hipMalloc /
-// hipFree.  Cached bytes are capped; the largest blocks go first.
+// sessions, so admission and closing seldom call hipMalloc / hipFree.
+// Requests are rounded up to GRANULE; a cached block is reused for a request
+// when it is at most 1/8 larger.  Blocks handed out plus blocks cached never
+// exceed the budget: cached blocks (largest first) are freed before a new
+// allocation would pass it.  Thread-safe.
 class Pool : public DeviceAllocator {
 public:
-    explicit Pool(size_t cap) : cap_(cap) {}
+    static constexpr size_t GRANULE = 65536;
+    explicit Pool(size_t budget) : budget_(budget) {}
     ~Pool() override { trim(0); }
-    void* acquire(size_t bytes) override {
+    void* acquire(size_t bytes, size_t* granted) override {
+        std::lock_guard<std::mutex> lk(mu_);
         bytes = round(bytes);
         auto it = free_.lower_bound(bytes);
-        if (it != free_.end() && it->first <= 2 * bytes) {
+        if (it != free_.end() && it->first <= bytes + bytes / 8) {
             void* p = it->second;
-            cached_ -= it->first;
-            size_[p] = it->first;
+            const size_t sz = it->first;
+            cached_ -= sz;
+            used_ += sz;
+            size_[p] = sz;
             free_.erase(it);
+            *granted = sz;
             return p;
         }
+        // keep used + cached + bytes within the budget
+        trim(budget_ > used_ + bytes ? budget_ - used_ - bytes : 0);
         void* p = nullptr;
         if (hipMalloc(&p, bytes) != hipSuccess) {
             trim(0);  // give cached memory back and try once more
             if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
         }
+        used_ += bytes;
         size_[p] = bytes;
+        *granted = bytes;
         return p;
     }
     void release(void* p, size_t) override {
+        std::lock_guard<std::mutex> lk(mu_);
         auto it = size_.find(p);
         const size_t bytes = it->second;
         size_.erase(it);
+        used_ -= bytes;
         free_.emplace(bytes, p);
         cached_ += bytes;
-        trim(cap_);
+        trim(budget_ > used_ ? budget_ - used_ : 0);
     }
-    size_t cached() const { return cached_; }
+    // device bytes held: handed out plus cached
+    size_t held() {
+        std::lock_guard<std::mutex> lk(mu_);
+        return used_ + cached_;
+    }
+    static size_t round(size_t b) { return (b + GRANULE - 1) / GRANULE * GRANULE; }
 
 private:
-    static size_t round(size_t b) { return (b + 65535) & ~size_t(65535); }
-    void trim(size_t limit) {
+    void trim(size_t limit) {  // caller holds mu_ (or is the destructor)
         while (cached_ > limit && !free_.empty()) {
             auto it = std::prev(free_.end());
             (void)hipFree(it->second);
@@ -103,8 +125,9 @@ private:
             free_.erase(it);
         }
     }
-    size_t cap_;
-    size_t cached_ = 0;
+    std::mutex mu_;
+    size_t budget_;
+    size_t used_ = 0, cached_ = 0;
     std::multimap<size_t, void*> free_;
     std::map<void*, size_t> size_;
 };
@@ -119,8 +142,13 @@ struct pg_server {
     std::string err;
     Pool* pool = nullptr;
 
+    hipStream_t upload_stream = nullptr;  // session uploads (default priority)
+
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_done, cv_upload;
+    std::deque<int64_t> upload_q;          // admitted sessions awaiting their upload
+    std::thread uploader;
+    bool stop_upload = false;              // set once the worker has ended
     std::map<int64_t, Session> sessions;   // ordered by id = arrival order
     std::deque<int64_t> admit_q;
     std::map<int64_t, Call> calls;
@@ -139,6 +167,7 @@ struct pg_server {
     // statistics
     int64_t steps = 0, calls_done = 0, batched_calls = 0, max_batch = 0, admitted_total = 0;
     int64_t max_waiting = 0;
+    int64_t peak_held = 0;                 // largest device bytes held by the pool
 };
 
 namespace {
@@ -160,11 +189,12 @@ int grow(pg_server* s, void** h, void** d, size_t* cap, size_t need) {
     return PG_OK;
 }
 
-// Admit waiting sessions in arrival order while they fit.  Caller holds mu.
+// Admit waiting sessions in arrival order while they fit: reserve their
+// bytes and hand them to the upload thread.  Caller holds mu.
 void admit(pg_server* s) {
     int admitted = 0;
     for (auto& kv : s->sessions)
-        if (kv.second.admitted) ++admitted;
+        if (kv.second.state != Session::WAITING) ++admitted;
     while (!s->admit_q.empty()) {
         auto it = s->sessions.find(s->admit_q.front());
         if (it == s->sessions.end()) {
@@ -172,11 +202,47 @@ void admit(pg_server* s) {
             continue;
         }
         Session& ss = it->second;
-        if (admitted >= s->max_sessions || s->in_use + ss.footprint > s->budget) break;
+        if (admitted >= s->max_sessions || s->in_use + ss.reserve > s->budget) break;
         s->admit_q.pop_front();
-        const int r = ctx_prepare(ss.ctx);
+        ss.state = Session::UPLOADING;
+        ss.charged = ss.reserve;
+        s->in_use += ss.charged;
+        s->peak = std::max(s->peak, s->in_use);
+        ++admitted;
+        ++s->admitted_total;
+        s->upload_q.push_back(it->first);
+        s->cv_upload.notify_one();
+    }
+    s->max_waiting = std::max<int64_t>(s->max_waiting, (int64_t)s->admit_q.size());
+}
+
+// Upload thread: allocate and copy each admitted session's device state on
+// its own stream, without the lock, while batches keep running.
+void upload_loop(pg_server* s) {
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        s->cv_upload.wait(lk, [&] { return s->stop_upload || !s->upload_q.empty(); });
+        if (s->upload_q.empty()) break;  // the worker has ended and nothing is left
+        const int64_t id = s->upload_q.front();
+        s->upload_q.pop_front();
+        Session& ss = s->sessions.at(id);  // not reaped while UPLOADING
+        pg_ctx* ctx = ss.ctx;
+        lk.unlock();
+        const int r = ctx_prepare(ctx, s->upload_stream);
+        const int64_t held = (int64_t)s->pool->held();
+        lk.lock();
+        s->peak_held = std::max(s->peak_held, held);
+        if (r == PG_OK) {
+            // charge what the pool actually handed out
+            const int64_t got = pg_device_bytes(ctx);
+            s->in_use += got - ss.charged;
+            ss.charged = got;
+            s->peak = std::max(s->peak, s->in_use);
+        }
         if (r != PG_OK) {
-            // fail every pending call of this session
+            // fail every pending call of this session and wake their waiters
+            s->err = ctx_error(ctx);
             for (int64_t tk : ss.pending) {
                 Call& c = s->calls[tk];
                 c.status = r;
@@ -185,23 +251,21 @@ void admit(pg_server* s) {
             }
             ss.pending.clear();
             ss.closing = true;
-            continue;
+            ss.state = Session::ADMITTED;  // reaped with its charge
+            s->cv_done.notify_all();
+        } else {
+            ss.state = Session::ADMITTED;
         }
-        ss.admitted = true;
-        s->in_use += ss.footprint;
-        s->peak = std::max(s->peak, s->in_use);
-        ++admitted;
-        ++s->admitted_total;
+        s->cv_work.notify_all();
     }
-    s->max_waiting = std::max<int64_t>(s->max_waiting, (int64_t)s->admit_q.size());
 }
 
 // Free sessions that asked to close and have no pending calls.  Caller holds mu.
 void reap(pg_server* s) {
     for (auto it = s->sessions.begin(); it != s->sessions.end();) {
         Session& ss = it->second;
-        if (ss.closing && ss.pending.empty()) {
-            if (ss.admitted) s->in_use -= ss.footprint;
+        if (ss.closing && ss.pending.empty() && ss.state != Session::UPLOADING) {
+            if (ss.state == Session::ADMITTED) s->in_use -= ss.charged;
             pg_destroy(ss.ctx);
             it = s->sessions.erase(it);
         } else {
@@ -315,13 +379,15 @@ void worker_loop(pg_server* s) {
         std::vector<Item> batch;
         for (auto& kv : s->sessions) {
             Session& ss = kv.second;
-            if (!ss.admitted || ss.pending.empty()) continue;
+            if (ss.state != Session::ADMITTED || ss.pending.empty()) continue;
             const int64_t tk = ss.pending.front();
             Call& c = s->calls[tk];
             batch.push_back(Item{tk, &ss, &c, ctx_args(ss.ctx)});
         }
         if (batch.empty()) {
-            if (s->stop) break;
+            bool uploading = !s->upload_q.empty();
+            for (auto& kv : s->sessions) uploading = uploading || kv.second.state == Session::UPLOADING;
+            if (s->stop && !uploading) break;
             s->cv_work.wait(lk);
             continue;
         }
@@ -379,11 +445,32 @@ int pg_server_create(int device, int precision, int64_t hbm_budget, int32_t max_
         delete s;
         return PG_E_DEVICE;
     }
+    if (hipStreamCreate(&s->upload_stream) != hipSuccess) {
+        (void)hipStreamDestroy(s->stream);
+        delete s;
+        return PG_E_DEVICE;
+    }
     s->pool = new Pool((size_t)hbm_budget);
     try {
         s->worker = std::thread(worker_loop, s);
     } catch (...) {
         delete s->pool;
+        (void)hipStreamDestroy(s->upload_stream);
+        (void)hipStreamDestroy(s->stream);
+        delete s;
+        return PG_E_DEVICE;
+    }
+    try {
+        s->uploader = std::thread(upload_loop, s);
+    } catch (...) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stop = true;
+        }
+        s->cv_work.notify_all();
+        s->worker.join();
+        delete s->pool;
+        (void)hipStreamDestroy(s->upload_stream);
         (void)hipStreamDestroy(s->stream);
         delete s;
         return PG_E_DEVICE;
@@ -403,6 +490,12 @@ void pg_server_destroy(pg_server* s) {
     if (s->worker.joinable()) s->worker.join();
     {
         std::lock_guard<std::mutex> lk(s->mu);
+        s->stop_upload = true;
+    }
+    s->cv_upload.notify_all();
+    if (s->uploader.joinable()) s->uploader.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
         for (auto& kv : s->sessions) pg_destroy(kv.second.ctx);
         s->sessions.clear();
     }
@@ -412,6 +505,7 @@ void pg_server_destroy(pg_server* s) {
     if (s->d_in) (void)hipFree(s->d_in);
     if (s->d_out) (void)hipFree(s->d_out);
     delete s->pool;
+    if (s->upload_stream) (void)hipStreamDestroy(s->upload_stream);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -437,10 +531,19 @@ int pg_server_open(pg_server* s, int32_t n_tips, const int32_t* parent, int32_t 
         pg_destroy(c);
         return r;
     }
-    const int64_t fp = pg_footprint_bytes(n_tips, n_patterns, n_states, n_cats, s->precision);
+    // host planning here, on the caller's thread; the reservation covers the
+    // pool's rounding and its reuse of blocks up to 1/8 larger
+    if ((r = ctx_plan(c)) != PG_OK) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->err = pg_last_error(c);
+        pg_destroy(c);
+        return r;
+    }
+    const int64_t need = ctx_need_bytes(c, Pool::GRANULE);
+    const int64_t reserve = need + need / 8;
     std::lock_guard<std::mutex> lk(s->mu);
-    if (fp > s->budget) {
-        s->err = "session needs " + std::to_string(fp) + " device bytes, more than the budget " +
+    if (reserve > s->budget) {
+        s->err = "session needs up to " + std::to_string(reserve) + " device bytes, more than the budget " +
                  std::to_string(s->budget);
         pg_destroy(c);
         return PG_E_OOM;
@@ -448,7 +551,7 @@ int pg_server_open(pg_server* s, int32_t n_tips, const int32_t* parent, int32_t 
     const int64_t id = s->next_session++;
     Session& ss = s->sessions[id];
     ss.ctx = c;
-    ss.footprint = fp;
+    ss.reserve = reserve;
     ss.n_branches = 2 * n_tips - 2;
     ss.M = n_states;
     s->admit_q.push_back(id);
@@ -518,10 +621,10 @@ int pg_server_stats(pg_server* s, int64_t* out, int32_t n) {
     std::lock_guard<std::mutex> lk(s->mu);
     int64_t admitted = 0;
     for (auto& kv : s->sessions)
-        if (kv.second.admitted) ++admitted;
+        if (kv.second.state != Session::WAITING) ++admitted;
     const int64_t v[PG_SRV_STAT_COUNT] = {s->steps,     s->calls_done, s->max_batch, s->admitted_total,
                                           admitted,     (int64_t)s->admit_q.size(), s->in_use, s->peak,
-                                          s->max_waiting};
+                                          s->max_waiting, s->peak_held};
     for (int i = 0; i < n && i < PG_SRV_STAT_COUNT; ++i) out[i] = v[i];
     return PG_OK;
 }

@@ -87,6 +87,7 @@ def test_admission_by_footprint(gpu):
     assert all(o[0] == B.PG_OK for o in out)
     assert stats["max_waiting"] >= 1, stats
     assert stats["peak_bytes"] <= budget, stats
+    assert 0 < stats["peak_held"] <= budget, stats   # pool blocks in use plus cached
     assert stats["admitted_total"] == 6
 
 
@@ -126,3 +127,37 @@ def test_stream_of_requests(gpu):
     for w, out in zip(ws[:3], res["results"][:3]):
         l, g = _single(w, B.PG_FP32)
         assert out[0][0] == l and np.array_equal(out[0][1], g)
+
+
+def test_failed_upload_wakes_waiting_caller(gpu):
+    """A session whose device buffers cannot be allocated (about 2 TB in
+    FP64) fails its queued calls with PG_E_OOM, and a thread already blocked
+    in pg_server_wait on one of them wakes up."""
+    import threading
+
+    from paper_1905_12146_amd.serving import Server
+    small_w = make_workload("C3", seed=11, n_tips=50, n_patterns=64, tips="uniform")
+    N, S, m, K = 1000, 100_000, 20, 64
+    huge = make_workload("C3", seed=12, n_tips=N, n_patterns=16, tips="uniform")
+    masks = np.full((N, S), (1 << m) - 1, dtype=np.uint64)  # every tip missing
+    Q = np.full((m, m), 1.0 / (m - 1))
+    np.fill_diagonal(Q, -1.0)
+    with Server(0, B.PG_FP64, 1 << 42, 1) as srv:
+        first = srv.open(small_w)              # holds the only session slot
+        st, _, _, _ = srv.wait(srv.submit(first, small_w.t), len(small_w.t))
+        assert st == B.PG_OK
+        sid = B.pg_server_open(srv.handle, huge.parent, masks, np.ones(S), Q, np.full(m, 1.0 / m),
+                               np.ones(K), np.full(K, 1.0 / K))
+        tk = srv.submit(sid, huge.t)
+        out = {}
+        waiter = threading.Thread(target=lambda: out.update(r=srv.wait(tk, len(huge.t))), daemon=True)
+        waiter.start()
+        srv.close(first)                       # admits the huge session, whose upload fails
+        waiter.join(timeout=60)
+        assert not waiter.is_alive(), "the waiting caller was not woken"
+        assert out["r"][0] == B.PG_E_OOM, out
+        srv.close(sid)
+        ok = srv.open(small_w)                 # the server keeps serving
+        st, _, _, _ = srv.wait(srv.submit(ok, small_w.t), len(small_w.t))
+        assert st == B.PG_OK
+        srv.close(ok)

@@ -209,6 +209,34 @@ int pg_logL_and_grad_device(pg_ctx* ctx, const double* d_t, double* d_logL,
  * are no resident partials. */
 int pg_grad_device(pg_ctx* ctx, double* d_grad);
 
+/* Allocation-free variant of pg_logL_and_grad_device, for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, passes
+ * and results (bit for bit) as pg_logL_and_grad_device; d_grad == NULL
+ * computes logL only.  It never calls hipMalloc, hipFree or any other
+ * allocating routine for device memory: every device buffer of the
+ * evaluation (tip codes, schedule, model tables, transition matrices,
+ * messages, pre-order vectors, root values, tile partials, status) lives in
+ * one library-owned array per device of PG_NOALLOC_MAX_BYTES bytes, which
+ * each GPU the library runs on holds until the process ends.  The inputs
+ * are copied into it from the context's host copies (set by pg_set_tree,
+ * pg_set_patterns, pg_set_model, pg_set_branch_models) on the context's
+ * stream at every call; host-side planning runs on the first call after
+ * one of those changes.  Problems needing more than PG_NOALLOC_MAX_BYTES
+ * (see pg_footprint_bytes for the scale) fail with PG_E_INVALID.
+ * Asynchronous like the device variant; errors of the evaluation itself (a
+ * bad branch length, a zero likelihood) show only as NaN or -inf in
+ * *d_logL (pg_status does not see them).  The context's own device buffers
+ * and resident partials are neither used nor changed (pg_grad and
+ * pg_grad_device keep referring to the last other evaluation).  Every call
+ * on one GPU shares that GPU's array, which keeps the last call's contents:
+ * calls that overlap on one GPU (on different streams, from different
+ * threads or contexts) race and give undefined results; calls in order on
+ * one stream are safe.  PG_E_DEVICE if the array's device address could not
+ * be found when the context was created. */
+#define PG_NOALLOC_MAX_BYTES (64ll << 20)
+int pg_logL_and_grad_noalloc(pg_ctx* ctx, const double* d_t, double* d_logL, double* d_grad);
+
 /* Device-side status of the last device-pointer evaluation (waits for the
  * stream): PG_OK, PG_E_INVALID (bad t) or PG_E_ZERO_LIK. */
 int pg_status(pg_ctx* ctx);

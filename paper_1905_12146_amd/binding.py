@@ -34,6 +34,7 @@ PG_SPLIT_BF16 = 2
 
 PG_K_PMAT, PG_K_POST, PG_K_ROOT, PG_K_PRE, PG_K_GSUM = range(5)
 PG_K_COUNT = 5
+PG_NOALLOC_MAX_BYTES = 64 << 20
 KERNEL_NAMES = ("pmat", "post", "root", "pre", "gsum")
 
 ERROR_NAMES = {
@@ -62,6 +63,7 @@ _SIGNATURES = [
     ("pg_hessian_diag", ctypes.c_int, [_vp, _vp, _vp]),
     ("pg_logL_and_grad_device", ctypes.c_int, [_vp, _vp, _vp, _vp]),
     ("pg_grad_device", ctypes.c_int, [_vp, _vp]),
+    ("pg_logL_and_grad_noalloc", ctypes.c_int, [_vp, _vp, _vp, _vp]),
     ("pg_status", ctypes.c_int, [_vp]),
     ("pg_set_timing", ctypes.c_int, [_vp, ctypes.c_int]),
     ("pg_get_timing", ctypes.c_int, [_vp, _vp, _vp]),
@@ -228,6 +230,13 @@ def pg_logL_and_grad_device(ctx, d_t, d_logL, d_grad):
     """Device addresses (ints); asynchronous on the context's stream."""
     _check(ctx, load().pg_logL_and_grad_device(ctx, ctypes.c_void_p(d_t), ctypes.c_void_p(d_logL),
                                                ctypes.c_void_p(d_grad) if d_grad else None))
+
+
+def pg_logL_and_grad_noalloc(ctx, d_t, d_logL, d_grad):
+    """Device addresses (ints); asynchronous on the context's stream; every
+    device buffer in the library's per-device scratch array."""
+    _check(ctx, load().pg_logL_and_grad_noalloc(ctx, ctypes.c_void_p(d_t), ctypes.c_void_p(d_logL),
+                                                ctypes.c_void_p(d_grad) if d_grad else None))
 
 
 def pg_grad_device(ctx, d_grad):
@@ -415,6 +424,9 @@ class Context:
 
     def grad_device(self, d_grad):
         pg_grad_device(self.handle, d_grad)
+
+    def logL_and_grad_noalloc(self, d_t, d_logL, d_grad):
+        pg_logL_and_grad_noalloc(self.handle, d_t, d_logL, d_grad)
 
     def status(self):
         return pg_status(self.handle)

@@ -8,12 +8,20 @@
 #include <cstring>
 #include <exception>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "pg_internal.h"
 
 using namespace pg;
+
+// Device scratch of the allocation-free entry point: every device buffer of
+// one of its evaluations, in one array per device, allocated with the code
+// object and held until the process ends.  In host code `scratch` names only
+// a host-side stand-in: its device address is looked up once per device,
+// with that device current (scratch_setup), and only that address is used.
+static __device__ __align__(256) unsigned char scratch[PG_NOALLOC_MAX_BYTES];
 
 namespace {
 
@@ -22,6 +30,14 @@ thread_local std::string g_create_error;
 struct DevBuf {
     void* ptr = nullptr;
     size_t bytes = 0;
+};
+
+// A buffer of the allocation-free entry point: its name, size, offset in
+// the device scratch and the host data it is uploaded from (or NULL).
+struct BufSpecRef {
+    const char* name;
+    size_t bytes, offset;
+    const void* src;
 };
 
 }  // namespace
@@ -71,6 +87,10 @@ struct pg_ctx {
     // device state
     bool dev_stale = true;        // host inputs changed since the last upload
     bool host_copies = false;     // copies from the host vectors may be in flight
+    // allocation-free evaluation: buffer layout in the device scratch
+    bool na_stale = true;
+    std::vector<BufSpecRef> na_specs;
+    size_t na_total = 0;
     bool have_partials = false;   // post-order pass results resident
     // partial re-evaluation: host copy of the branch lengths of the resident
     // partials (host-pointer evaluations only) and per-node exponents
@@ -476,6 +496,58 @@ int settle_host_copies(pg_ctx* c) {
     return PG_OK;
 }
 
+// ---------------------------------------------------------------- device scratch (see `scratch`)
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+bool g_scratch_done[SCRATCH_MAX_DEVICES] = {};
+hipError_t g_scratch_err[SCRATCH_MAX_DEVICES] = {};
+
+// Called by pg_create with `device` current.
+void scratch_setup(int device) {
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_done[device]) return;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_ptr[device] = (e == hipSuccess) ? p : nullptr;
+    g_scratch_err[device] = e;
+    g_scratch_done[device] = true;
+}
+
+// This device's scratch address, or NULL (with the reason in c->err).
+char* scratch_base(pg_ctx* c) {
+    if (c->device < 0 || c->device >= SCRATCH_MAX_DEVICES) {
+        fail(c, PG_E_DEVICE, "device index beyond the allocation-free entry point's table");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[c->device]) {
+        fail(c, PG_E_DEVICE, std::string("device scratch unavailable: ") +
+                                 (g_scratch_done[c->device] ? hipGetErrorString(g_scratch_err[c->device])
+                                                            : "not set up"));
+        return nullptr;
+    }
+    return static_cast<char*>(g_scratch_ptr[c->device]);
+}
+
+// Layout of the context's buffers in the scratch (256-byte aligned), kept
+// until the tree, patterns or model change.
+void plan_scratch(pg_ctx* c) {
+    if (!c->na_stale) return;
+    std::vector<BufSpec> specs = buffer_specs(ctx_dims(c), true);
+    attach_sources(c, specs);
+    c->na_specs.clear();
+    size_t off = 0;
+    for (const BufSpec& s : specs) {
+        off = (off + 255) & ~size_t(255);
+        c->na_specs.push_back(BufSpecRef{s.name, s.bytes, off, s.src});
+        off += s.bytes;
+    }
+    c->na_total = off;
+    c->na_stale = false;
+}
+
 // Allocate (or keep) the context's device buffers and upload its inputs.
 int upload(pg_ctx* c) {
     int r = check_ready(c);
@@ -698,6 +770,7 @@ int pg_create(int device, int precision, pg_ctx** out) {
         return PG_E_DEVICE;
     }
     c->stream = c->own_stream;
+    scratch_setup(device);
     *out = c;
     return PG_OK;
 }
@@ -752,6 +825,7 @@ int pg_set_tree(pg_ctx* c, int32_t N, const int32_t* parent) {
         build_levels(N, c->children.data(), c->lv);
         c->tree_set = true;
         c->dev_stale = true;
+        c->na_stale = true;
         c->plan_stale = true;
         c->have_partials = false;
         return PG_OK;
@@ -815,6 +889,7 @@ int pg_set_patterns(pg_ctx* c, int32_t S, int32_t m, const uint64_t* tip_masks, 
         c->weights.swap(w);
         c->patterns_set = true;
         c->dev_stale = true;
+        c->na_stale = true;
         c->have_partials = false;
         return PG_OK;
     });
@@ -880,6 +955,7 @@ int pg_set_model(pg_ctx* c, int32_t m, const double* Q, const double* pi, int32_
         if (old_m != m) c->bm_n = 0;  // branch models have the old state count
         c->model_set = true;
         c->dev_stale = true;
+        c->na_stale = true;
         c->plan_stale = true;
         c->have_partials = false;
         return PG_OK;
@@ -941,6 +1017,7 @@ int pg_set_branch_models(pg_ctx* c, int32_t n_models, const double* Q, const int
         c->bm_qnorm.swap(qn);
         c->bm_model.swap(model);
         c->dev_stale = true;
+        c->na_stale = true;
         c->have_partials = false;
         return PG_OK;
     });
@@ -1165,6 +1242,48 @@ int pg_grad_device(pg_ctx* c, double* d_grad) {
         // the logL reduction of the backward pass goes to the context's own
         // buffer, not to the caller's forward output
         return enqueue_backward(c, a);
+    });
+}
+
+int pg_logL_and_grad_noalloc(pg_ctx* c, const double* d_t, double* d_logL, double* d_grad) {
+    if (!c) return PG_E_INVALID;
+    if (!d_t || !d_logL) return fail(c, PG_E_INVALID, "NULL d_t or d_logL");
+    return guarded(c, [&] {
+        int r = check_ready(c);
+        if (r) return r;
+        PG_HIP(c, hipSetDevice(c->device));
+        if (c->plan_stale || c->na_stale) {
+            // host vectors are about to be re-read or replaced
+            if ((r = settle_host_copies(c))) return r;
+            ensure_plan(c);
+            plan_scratch(c);
+        }
+        if (c->na_total > (size_t)PG_NOALLOC_MAX_BYTES)
+            return fail(c, PG_E_INVALID, "the problem needs " + std::to_string(c->na_total) +
+                                             " bytes of device scratch; the allocation-free entry point has " +
+                                             std::to_string((long long)PG_NOALLOC_MAX_BYTES));
+        char* base = scratch_base(c);
+        if (!base) return PG_E_DEVICE;
+        // inputs from the context's host copies into this device's scratch
+        for (const BufSpecRef& s : c->na_specs)
+            if (s.src) PG_HIP(c, hipMemcpyAsync(base + s.offset, s.src, s.bytes, hipMemcpyHostToDevice, c->stream));
+        c->host_copies = true;
+        EvalArgs a;
+        fill_args(c, [&](const char* name) -> void* {
+            for (const BufSpecRef& s : c->na_specs)
+                if (std::strcmp(s.name, name) == 0) return base + s.offset;
+            return nullptr;
+        }, a);
+        a.t = d_t;
+        a.logL_out = d_logL;
+        a.grad_out = d_grad;
+        // no timing events here: creating them may allocate
+        const bool timing = c->timing;
+        c->timing = false;
+        r = enqueue_forward(c, a, d_grad == nullptr);
+        if (r == PG_OK && d_grad) r = enqueue_backward(c, a);
+        c->timing = timing;
+        return r;
     });
 }
 

@@ -69,7 +69,7 @@ extern "C" {
  *          pg_set_model (scaling and squaring when Q is not usably
  *          diagonalisable; see pg_eigensystem).  Any 2 <= n_states <= 64
  *          (padded to 64); meant for large state spaces such as 61 codons.
- *          No Hessian. */
+ *          The Hessian's Q^2 products are split the same way. */
 #define PG_FP64 0
 #define PG_FP32 1
 #define PG_SPLIT_BF16 2
@@ -185,8 +185,9 @@ int pg_grad(pg_ctx* ctx, double* grad);
 
 /* Diagonal of the Hessian, d2 logL / dt_b^2, Section 2.7 Eq. (Hessian),
  * on the partials left by the last pg_logL or pg_logL_and_grad.  Also
- * returns the gradient in grad[2N-2] unless grad == NULL.  Blocks.
- * PG_E_UNSUPPORTED on a PG_SPLIT_BF16 context. */
+ * returns the gradient in grad[2N-2] unless grad == NULL.  Blocks.  Every
+ * precision; the second-derivative numerators use Q^2 of each branch's
+ * rate matrix (split-BF16: Q^2 carried in three BF16 parts). */
 int pg_hessian_diag(pg_ctx* ctx, double* grad, double* hess);
 
 /* Device-pointer variant of pg_logL_and_grad (same passes and sections):
@@ -290,8 +291,9 @@ int pg_eigensystem(int32_t m, const double* Q, double* V, double* Vinv, double* 
  * grad (caller-allocated, 2N-2), and reports the time from submit to
  * completion.  pg_server_close lets the session's queued calls finish, then
  * frees its device memory, which admits waiting sessions.  If a session's
- * upload fails, its queued calls complete with that error.  Server functions
- * are thread-safe. */
+ * upload fails, its queued calls complete with that error and the server
+ * closes the session (pg_server_close then returns PG_E_STATE).  Server
+ * functions are thread-safe. */
 typedef struct pg_server pg_server;
 
 /* Errors: PG_E_INVALID (NULL, budget <= 0, max_sessions < 1), PG_E_DEVICE,

@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libphylograd.so")
-SOURCES = ["kernels.hip", "kernels_mfma.hip", "capi.cpp", "server.cpp", "eigen.cpp", "plan.cpp"]
+SOURCES = ["kernels.hip", "kernels_mfma.hip", "kernels_dense.hip", "capi.cpp", "server.cpp", "eigen.cpp", "plan.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++20", "-fPIC", "--offload-arch=gfx950",

@@ -74,12 +74,14 @@ struct pg_ctx {
     std::vector<int> eKind;
     bool expm_taylor = false;
     double eig_cond = 0.0, eig_resid = 0.0;
-    std::vector<uint16_t> Qop;
+    std::vector<uint16_t> Qop, Q2op;
     // non-homogeneous model: branch b uses bm_Q[bm_model[b]] (bm_n = 0: off)
     int bm_n = 0;
     std::vector<double> bm_Q, bm_Q2, bm_qnorm;
     std::vector<int> bm_model;
 
+    // dense-state path: Q and Q^2 as matrix-core fragments (bytes)
+    std::vector<uint8_t> qfrag;
     // traversal plan of the tree for the model's state count
     TraversalPlan plan;
     bool plan_stale = true;
@@ -217,22 +219,27 @@ void prepare_split_model(pg_ctx* c) {
             c->eKind[j] = es.kind[j];
         }
     }
-    c->Qop.assign(MF_QOP_BYTES / 2, 0);
-    for (int mt = 0; mt < 4; ++mt)
-        for (int ks = 0; ks < 2; ++ks)
-            for (int lane = 0; lane < 64; ++lane)
-                for (int j = 0; j < 8; ++j) {
-                    const int r = 16 * mt + lane % 16;
-                    const int y = 16 * (2 * ks + j / 4) + 4 * (lane / 16) + j % 4;
-                    const double v = (r < m && y < m) ? c->Q[r * m + y] : 0.0;
-                    const uint16_t hi = bf16_bits((float)v);
-                    const double r1 = v - (double)bf16_value(hi);
-                    const uint16_t mid = bf16_bits((float)r1);
-                    const uint16_t lo = bf16_bits((float)(r1 - (double)bf16_value(mid)));
-                    const uint16_t parts[3] = {hi, mid, lo};
-                    for (int part = 0; part < 3; ++part)
-                        c->Qop[((((mt * 2 + ks) * 3 + part) * 64 + lane) * 8) + j] = parts[part];
-                }
+    // Q (gradient) and Q^2 (Hessian)
+    auto operands = [&](const std::vector<double>& A, std::vector<uint16_t>& out) {
+        out.assign(MF_QOP_BYTES / 2, 0);
+        for (int mt = 0; mt < 4; ++mt)
+            for (int ks = 0; ks < 2; ++ks)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int j = 0; j < 8; ++j) {
+                        const int r = 16 * mt + lane % 16;
+                        const int y = 16 * (2 * ks + j / 4) + 4 * (lane / 16) + j % 4;
+                        const double v = (r < m && y < m) ? A[r * m + y] : 0.0;
+                        const uint16_t hi = bf16_bits((float)v);
+                        const double r1 = v - (double)bf16_value(hi);
+                        const uint16_t mid = bf16_bits((float)r1);
+                        const uint16_t lo = bf16_bits((float)(r1 - (double)bf16_value(mid)));
+                        const uint16_t parts[3] = {hi, mid, lo};
+                        for (int part = 0; part < 3; ++part)
+                            out[((((mt * 2 + ks) * 3 + part) * 64 + lane) * 8) + j] = parts[part];
+                    }
+    };
+    operands(c->Q, c->Qop);
+    operands(c->Q2, c->Q2op);
 }
 
 int check_tree(pg_ctx* c, int32_t N, const int32_t* parent) {
@@ -290,7 +297,7 @@ void ensure_plan(pg_ctx* c) {
     p.n_states = c->m;
     p.elem_bytes = (int)elem_size(c->precision);
     p.clades = !split && c->m * c->m <= TP;
-    p.top_region = !split;
+    p.top_region = !split && !dense_states(c->m);
     p.ns_post = split ? node_slots(c->m) : post_node_slots(c->m, c->precision);
     p.ns_pre = split ? p.ns_post : pre_node_slots(c->m, c->precision);
     TraversalPlan plan;
@@ -319,14 +326,16 @@ struct BufSpec {
 // the Hessian's tile sums, the per-node exponents).
 std::vector<BufSpec> buffer_specs(const Dims& d, bool lean) {
     const bool split = d.precision == PG_SPLIT_BF16;
+    const bool dense = !split && dense_states((int)d.M);
     const size_t es = elem_size(d.precision);
     const size_t N = d.N, B = 2 * d.N - 2, M = d.M, K = d.K, S_pad = d.S_pad;
     const size_t n_pb = S_pad / TP, n_tiles = K * n_pb;
-    const size_t vec = K * (split ? MP : M) * S_pad;
+    const size_t vec = K * (split ? MP : dense ? dn_md((int)M) : M) * S_pad;
     std::vector<BufSpec> v;
     auto add = [&](const char* name, size_t bytes) { v.push_back(BufSpec{name, bytes}); };
     if (!lean) add("t", sizeof(double) * B);
-    add("P", split ? MF_SLOT_BYTES * B * K : es * B * K * M * M);
+    add("P", split ? MF_SLOT_BYTES * B * K : es * B * K * (dense ? dn_slot_elems((int)M) : M * M));
+    if (dense) add("Qfrag", es * std::max<size_t>(1, d.bm_n) * dn_qfrag_elems((int)M));
     if (split) {
         add("eV", sizeof(double) * MP * MP);
         add("eVinv", sizeof(double) * MP * MP);
@@ -334,6 +343,7 @@ std::vector<BufSpec> buffer_specs(const Dims& d, bool lean) {
         add("eIm", sizeof(double) * MP);
         add("eKind", sizeof(int) * MP);
         add("Qop", MF_QOP_BYTES);
+        add("Q2op", MF_QOP_BYTES);
     }
     add("msg", es * vec * (N - 1));
     add("qv", es * vec * (N - 1));
@@ -390,12 +400,12 @@ void attach_sources(const pg_ctx* c, std::vector<BufSpec>& specs) {
     static_assert(sizeof(Ent) == sizeof(int4), "schedule entries are uploaded as int4");
     const std::map<std::string, const void*> src = {
         {"eV", c->eV.data()}, {"eVinv", c->eVinv.data()}, {"eRe", c->eRe.data()}, {"eIm", c->eIm.data()},
-        {"eKind", c->eKind.data()}, {"Qop", c->Qop.data()}, {"codes", c->codes.data()},
+        {"eKind", c->eKind.data()}, {"Qop", c->Qop.data()}, {"Q2op", c->Q2op.data()}, {"codes", c->codes.data()},
         {"masks", c->masks.data()}, {"level_off", c->plan.level_off.data()}, {"sched", c->plan.sched.data()},
         {"cl_off", c->plan.cl_off.data()}, {"Q64", c->Q.data()}, {"Q2_64", c->Q2.data()},
         {"pi64", c->pi.data()}, {"rates", c->rates.data()}, {"catw", c->catw.data()},
         {"weights", c->weights.data()}, {"bm_Q", c->bm_Q.data()}, {"bm_Q2", c->bm_Q2.data()},
-        {"bm_qnorm", c->bm_qnorm.data()}, {"bm_model", c->bm_model.data()}};
+        {"bm_qnorm", c->bm_qnorm.data()}, {"bm_model", c->bm_model.data()}, {"Qfrag", c->qfrag.data()}};
     for (BufSpec& s : specs) {
         auto it = src.find(s.name);
         if (it != src.end()) s.src = it->second;
@@ -482,8 +492,40 @@ void fill_args(const pg_ctx* c, At&& at, EvalArgs& a) {
         a.eIm = static_cast<const double*>(at("eIm"));
         a.eKind = static_cast<const int*>(at("eKind"));
         a.Qop = at("Qop");
+        a.Q2op = at("Q2op");
         a.expm_taylor = c->expm_taylor ? 1 : 0;
     }
+    a.Qfrag = at("Qfrag");
+}
+
+// Dense-state path: the A fragments of Q and Q^2 of every rate matrix (the
+// model's, or each per-branch matrix) in the vectors' type, [model][Q, Q^2]
+// [ob][s][lane] (layout in pg_internal.h).
+void prepare_dense_q(pg_ctx* c) {
+    const int M = c->m;
+    c->qfrag.clear();
+    if (c->precision == PG_SPLIT_BF16 || !dense_states(M)) return;
+    const int NF = dn_nf(M), KS = dn_ks(M);
+    const size_t es = elem_size(c->precision);
+    const int n = c->bm_n > 0 ? c->bm_n : 1;
+    c->qfrag.assign(es * (size_t)n * dn_qfrag_elems(M), 0);
+    for (int k = 0; k < n; ++k)
+        for (int which = 0; which < 2; ++which) {
+            const double* A = c->bm_n > 0 ? (which ? &c->bm_Q2[(size_t)k * M * M] : &c->bm_Q[(size_t)k * M * M])
+                                          : (which ? c->Q2.data() : c->Q.data());
+            for (int f = 0; f < NF; ++f)
+                for (int L = 0; L < 64; ++L) {
+                    const int x = dn_row_state(M, f / KS, L % 16, es == 8),
+                              y = dn_col_state(M, f % KS, L / 16, es == 8);
+                    const double v = (x >= 0 && y >= 0) ? A[x * M + y] : 0.0;
+                    const size_t i = (((size_t)k * 2 + which) * NF + f) * 64 + L;
+                    if (es == 8) std::memcpy(&c->qfrag[8 * i], &v, 8);
+                    else {
+                        const float fv = (float)v;
+                        std::memcpy(&c->qfrag[4 * i], &fv, 4);
+                    }
+                }
+        }
 }
 
 // Copies made from the context's pageable host vectors by the
@@ -535,6 +577,7 @@ char* scratch_base(pg_ctx* c) {
 // until the tree, patterns or model change.
 void plan_scratch(pg_ctx* c) {
     if (!c->na_stale) return;
+    prepare_dense_q(c);
     std::vector<BufSpec> specs = buffer_specs(ctx_dims(c), true);
     attach_sources(c, specs);
     c->na_specs.clear();
@@ -556,6 +599,7 @@ int upload(pg_ctx* c) {
     PG_HIP(c, hipSetDevice(c->device));
     if ((r = settle_host_copies(c))) return r;
     ensure_plan(c);
+    prepare_dense_q(c);
     std::vector<BufSpec> specs = buffer_specs(ctx_dims(c), false);
     attach_sources(c, specs);
     for (const BufSpec& s : specs)
@@ -1190,8 +1234,6 @@ int pg_logL_and_grad(pg_ctx* c, const double* t, double* logL, double* grad) {
 int pg_hessian_diag(pg_ctx* c, double* grad, double* hess) {
     if (!c) return PG_E_INVALID;
     if (!hess) return fail(c, PG_E_INVALID, "NULL hess");
-    if (c->precision == PG_SPLIT_BF16)
-        return fail(c, PG_E_UNSUPPORTED, "the Hessian diagonal has no split-BF16 kernel");
     if (!c->have_partials || c->dev_stale)
         return fail(c, PG_E_STATE, "no resident partials: call pg_logL first");
     return guarded(c, [&] {

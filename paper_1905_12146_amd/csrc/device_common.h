@@ -9,6 +9,17 @@
 
 namespace pg {
 
+// XCD-aware tile order: workgroups are dispatched round-robin over the 8
+// XCDs (block b runs on XCD b % 8), so block b takes tile
+// (b % 8) * per + b / 8 and each XCD walks a contiguous range of tiles: one
+// or two categories, whose transition-matrix fragments then stay in that
+// XCD's L2 while its tiles walk the same tree levels.  The grid has
+// 8 * per blocks; blocks past the last tile return at once.
+constexpr int N_XCD = 8;
+__host__ __device__ inline int xcd_per(int n_tiles) { return (n_tiles + N_XCD - 1) / N_XCD; }
+__device__ inline int xcd_tile(int b, int n_tiles) { return (b % N_XCD) * xcd_per(n_tiles) + b / N_XCD; }
+
+
 __device__ inline int exp_of(double x) { int e; (void)frexp(x, &e); return e; }
 __device__ inline int exp_of(float x) { int e; (void)frexpf(x, &e); return e; }
 __device__ inline double pow2_scale(double x, int e) { return ldexp(x, e); }

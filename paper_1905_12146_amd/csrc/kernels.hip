@@ -26,6 +26,7 @@
 // which equals Eq. (GradientWithGamma) of Section 2.6: u^T m is L_{s,l} up
 // to the category's own scale factor, which cancels in each ratio.
 #include "device_common.h"
+#include "expm_lds.h"
 
 #include <utility>
 
@@ -239,19 +240,6 @@ __device__ inline void lds_barrier() {
 // A branch length that is negative or not finite gives a NaN matrix, which
 // propagates to a NaN logL.
 
-constexpr int TAYLOR_DEG = 16;
-
-// Rate matrix and its norm on branch b: the model's, or the branch's own
-// in a non-homogeneous model.
-__device__ inline const double* branch_q(const EvalArgs& a, int b, int M) {
-    return a.n_models ? a.Qm + (size_t)a.branch_model[b] * M * M : a.Q64;
-}
-__device__ inline double branch_qnorm(const EvalArgs& a, int b) {
-    return a.n_models ? a.qnorm_m[a.branch_model[b]] : a.qnorm;
-}
-
-__device__ inline bool bad_length(double t) { return !(t >= 0.0) || isinf(t); }
-
 template <int M>
 __device__ inline void matmul_reg(const double A[M][M], const double B[M][M], double C[M][M]) {
 #pragma unroll
@@ -320,53 +308,10 @@ __device__ inline void pmat_lds_body(const EvalArgs& a, int block) {
     __shared__ double A[M * M], G[M * M], W[M * M];
     const int idx = block;
     const int b = a.blist ? a.blist[idx / a.K] : idx / a.K, l = idx % a.K;
-    const double tb = a.t[b];
     T* out = static_cast<T*>(a.P) + ((size_t)b * a.K + l) * M * M;
-    if (bad_length(tb)) {
+    if (!taylor_F_lds<M>(a, b, l, A, G, W)) {
         for (int e = threadIdx.x; e < M * M; e += blockDim.x) out[e] = T(NAN);
         return;
-    }
-    const double h = a.rates[l] * tb;
-    const double* Qb = branch_q(a, b, M);
-    double nrm = branch_qnorm(a, b) * h;
-    int s = 0;
-    while (nrm > 0.5 && s < 1100) { nrm *= 0.5; ++s; }
-    const double hs = ldexp(h, -s);
-    for (int e = threadIdx.x; e < M * M; e += blockDim.x) {
-        A[e] = Qb[e] * hs;
-        G[e] = (e / M == e % M) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    for (int k = TAYLOR_DEG; k >= 2; --k) {
-        const double inv = 1.0 / k;
-        for (int e = threadIdx.x; e < M * M; e += blockDim.x) {
-            const int i = e / M, j = e % M;
-            double acc = 0.0;
-            for (int q = 0; q < M; ++q) acc = fma(A[i * M + q], G[q * M + j], acc);
-            W[e] = acc;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < M * M; e += blockDim.x)
-            G[e] = ((e / M == e % M) ? 1.0 : 0.0) + W[e] * inv;
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < M * M; e += blockDim.x) {
-        const int i = e / M, j = e % M;
-        double acc = 0.0;
-        for (int q = 0; q < M; ++q) acc = fma(A[i * M + q], G[q * M + j], acc);
-        W[e] = acc;
-    }
-    __syncthreads();
-    for (int r = 0; r < s; ++r) {
-        for (int e = threadIdx.x; e < M * M; e += blockDim.x) {
-            const int i = e / M, j = e % M;
-            double acc = 0.0;
-            for (int q = 0; q < M; ++q) acc = fma(W[i * M + q], W[q * M + j], acc);
-            G[e] = acc;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < M * M; e += blockDim.x) W[e] = 2.0 * W[e] + G[e];
-        __syncthreads();
     }
     for (int e = threadIdx.x; e < M * M; e += blockDim.x)
         out[e] = T(((e / M == e % M) ? 1.0 : 0.0) + W[e]);
@@ -1175,17 +1120,19 @@ static hipError_t pmat_launch(const EvalArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// The small-state kernels of this file (M = 4); the dense-state path
+// (kernels_dense.hip) takes 16 < M <= 32 and the split-BF16 path
+// (kernels_mfma.hip) any M for PG_SPLIT_BF16.
 #define PG_DISPATCH(FN, ...)                                                     \
     do {                                                                         \
         if (a.M == 4 && precision == PG_FP64) return FN<4, double>(__VA_ARGS__);   \
         if (a.M == 4 && precision == PG_FP32) return FN<4, float>(__VA_ARGS__);    \
-        if (a.M == 20 && precision == PG_FP64) return FN<20, double>(__VA_ARGS__); \
-        if (a.M == 20 && precision == PG_FP32) return FN<20, float>(__VA_ARGS__);  \
         return hipErrorInvalidValue;                                             \
     } while (0)
 
 hipError_t launch_pmat(const EvalArgs& a, int precision, hipStream_t st) {
     if (precision == PG_SPLIT_BF16) return launch_mfma_pmat(a, st);
+    if (dense_states(a.M)) return launch_dense_pmat(a, precision, st);
     PG_DISPATCH(pmat_launch, a, st);
 }
 
@@ -1197,6 +1144,7 @@ static hipError_t post_launch(const EvalArgs& a, hipStream_t st) {
 
 hipError_t launch_post(const EvalArgs& a, int precision, hipStream_t st) {
     if (precision == PG_SPLIT_BF16) return launch_mfma_post(a, st);
+    if (dense_states(a.M)) return launch_dense_post(a, precision, st);
     PG_DISPATCH(post_launch, a, st);
 }
 
@@ -1220,7 +1168,8 @@ static hipError_t pre_launch(const EvalArgs& a, hipStream_t st, bool hess) {
 }
 
 hipError_t launch_pre(const EvalArgs& a, int precision, hipStream_t st, bool hess) {
-    if (precision == PG_SPLIT_BF16) return hess ? hipErrorInvalidValue : launch_mfma_pre(a, st);
+    if (precision == PG_SPLIT_BF16) return launch_mfma_pre(a, st, hess);
+    if (dense_states(a.M)) return launch_dense_pre(a, precision, st, hess);
     PG_DISPATCH(pre_launch, a, st, hess);
 }
 
@@ -1299,8 +1248,12 @@ hipError_t launch_batch(const BatchLaunch& b, hipStream_t st) {
     const int M = b.M, precision = b.precision;
     if (M == 4 && precision == PG_FP64) return batch_launch<4, double>(b, st);
     if (M == 4 && precision == PG_FP32) return batch_launch<4, float>(b, st);
-    if (M == 20 && precision == PG_FP64) return batch_launch<20, double>(b, st);
-    if (M == 20 && precision == PG_FP32) return batch_launch<20, float>(b, st);
+    if (dense_states(M)) {
+        const hipError_t e = launch_dense_batch(b, st);
+        if (e != hipSuccess) return e;
+        gsum_batch<<<b.gsum_blocks, GS_THREADS, 0, st>>>(b.reqs, b.gsum_map);
+        return hipGetLastError();
+    }
     return hipErrorInvalidValue;
 }
 

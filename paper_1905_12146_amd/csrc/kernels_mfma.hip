@@ -54,16 +54,6 @@ struct V16 {
     f32x4 v[4];
 };
 
-// XCD-aware tile order: workgroups are dispatched round-robin over the 8
-// XCDs (block b runs on XCD b % 8), so block b takes tile
-// (b % 8) * per + b / 8 and each XCD walks a contiguous range of tiles: one
-// or two categories, whose transition-matrix fragments then stay in that
-// XCD's L2 while its tiles walk the same tree levels.  The grid has
-// 8 * per blocks; blocks past the last tile return at once.
-constexpr int N_XCD = 8;
-__host__ __device__ inline int xcd_per(int n_tiles) { return (n_tiles + N_XCD - 1) / N_XCD; }
-__device__ inline int xcd_tile(int b, int n_tiles) { return (b % N_XCD) * xcd_per(n_tiles) + b / N_XCD; }
-
 __device__ inline size_t mvec_off(const EvalArgs& a, int node, int tile) {
     return ((size_t)(node - a.n_tips) * a.n_tiles + tile) * (size_t)(MP * TP);
 }
@@ -523,9 +513,14 @@ __device__ inline void mfma_post_body(const EvalArgs& a, int tile, int4* lds_sch
 // Child c under a node, with its top-of-branch vector u = q o m_sibling:
 //   ratio = (u^T Q m_c) / (u^T m_c), tile sum of g * ratio,
 //   and for an internal c: q_c = P_c^T u = u + F_c^T u, rescaled, stored
-// (F holds F_c^T's fragments, issued by the caller).
-__device__ inline void mfma_pre_child(const EvalArgs& a, int c, int tile, int lane, const Coef& cf, const V16& u,
-                                      const V16& mown, const bf16x8* qop, const Frags& F) {
+// (F holds F_c^T's fragments, issued by the caller).  HESS adds, for
+// Section 2.7, the tile sum of h * (u^T Q^2 m_c) / (u^T m_c) and the
+// per-pattern rho gamma ratio (reduced by hsum_kernel); Q^2's fragments
+// are read from memory (q2op).
+template <bool HESS>
+__device__ inline void mfma_pre_child(const EvalArgs& a, int c, int l, int tile, int s, int lane, const Coef& cf,
+                                      const V16& u, const V16& mown, const bf16x8* qop, const bf16x8* q2op,
+                                      const Frags& F) {
     float den = 0.f;
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
@@ -546,6 +541,23 @@ __device__ inline void mfma_pre_child(const EvalArgs& a, int c, int tile, int la
     double term = (cf.g > 0.0) ? cf.g * ratio : 0.0;
     term = sum16(term);  // every row holds the same 16 patterns
     if (lane == 0) a.partial[(size_t)tile * a.n_branches + c] = term;
+    if constexpr (HESS) {
+        V16 q2m;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) q2m.v[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        apply3(q2op, lane, mown, q2m);
+        float num2 = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) num2 = fmaf(u.v[mt][i], q2m.v[mt][i], num2);
+        num2 = xsum4(num2);
+        const double ratio2 = (den > 0.f) ? (double)num2 / (double)den : 0.0;
+        double term2 = (cf.h > 0.0) ? cf.h * ratio2 : 0.0;
+        term2 = sum16(term2);
+        if (lane == 0) a.partial2[(size_t)tile * a.n_branches + c] = term2;
+        if ((lane >> 4) == 0) a.r1[((size_t)c * a.K + l) * a.S_pad + s] = (cf.nw > 0.0) ? cf.nw * ratio : 0.0;
+    }
     if (c >= a.n_tips) {
         V16 acc = u;
         apply3f(F, u, acc);
@@ -561,6 +573,7 @@ __device__ inline void codes_issue(const EvalArgs& a, int4 nd, int s, unsigned& 
     if (nd.z < a.n_tips) cj = a.codes[(size_t)nd.z * a.S_pad + s];
 }
 
+template <bool HESS>
 __device__ inline void mfma_pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
     __shared__ bf16x8 qop[3 * 8 * 64];
     const int l = tile / a.n_pb, pb = tile % a.n_pb;
@@ -575,6 +588,7 @@ __device__ inline void mfma_pre_body(const EvalArgs& a, int tile, int4* lds_sche
         if (l == 0 && wv == 0 && g == 0) logl_block_part(a, pb, ps, r);
     }
     const bf16x8* qsrc = static_cast<const bf16x8*>(a.Qop);
+    const bf16x8* q2op = static_cast<const bf16x8*>(a.Q2op);
     for (int i = threadIdx.x; i < 3 * 8 * 64; i += blockDim.x) qop[i] = qsrc[i];
     stage_schedule(a, lds_sched);
     __syncthreads();
@@ -619,11 +633,11 @@ __device__ inline void mfma_pre_body(const EvalArgs& a, int tile, int4* lds_sche
                     ui.v[mt] = q.v[mt] * mj.v[mt];
                     uj.v[mt] = q.v[mt] * mi.v[mt];
                 }
-                mfma_pre_child(a, nd.y, tile, lane, cf, ui, mi, qop, F);
+                mfma_pre_child<HESS>(a, nd.y, l, tile, s, lane, cf, ui, mi, qop, q2op, F);
                 // the second child's fragments load under its Q product
                 __builtin_amdgcn_sched_barrier(0);
                 if (nd.z >= a.n_tips) frags_issue(frag_of(a, nd.z, l, 1), lane, F);
-                mfma_pre_child(a, nd.z, tile, lane, cf, uj, mj, qop, F);
+                mfma_pre_child<HESS>(a, nd.z, l, tile, s, lane, cf, uj, mj, qop, q2op, F);
                 if (!more) break;
                 nd = nn;
                 ci = ni;
@@ -646,11 +660,12 @@ __global__ void __launch_bounds__(MF_THREADS) mfma_post_kernel(EvalArgs a) {
     mfma_post_body(a, tile, lds_dyn);
 }
 
+template <bool HESS>
 __global__ void __launch_bounds__(MF_THREADS) mfma_pre_kernel(EvalArgs a) {
     extern __shared__ int4 lds_dyn[];
     const int tile = xcd_tile(blockIdx.x, a.n_tiles);
     if (tile >= a.n_tiles) return;
-    mfma_pre_body(a, tile, lds_dyn);
+    mfma_pre_body<HESS>(a, tile, lds_dyn);
 }
 
 size_t mfma_post_lds_bytes(const EvalArgs& a) { return sched_lds_bytes(a); }
@@ -666,8 +681,10 @@ hipError_t launch_mfma_post(const EvalArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_mfma_pre(const EvalArgs& a, hipStream_t st) {
-    mfma_pre_kernel<<<N_XCD * xcd_per(a.n_tiles), MF_THREADS, mfma_pre_lds_bytes(a), st>>>(a);
+hipError_t launch_mfma_pre(const EvalArgs& a, hipStream_t st, bool hess) {
+    const dim3 grid(N_XCD * xcd_per(a.n_tiles)), block(MF_THREADS);
+    if (hess) mfma_pre_kernel<true><<<grid, block, mfma_pre_lds_bytes(a), st>>>(a);
+    else mfma_pre_kernel<false><<<grid, block, mfma_pre_lds_bytes(a), st>>>(a);
     return hipGetLastError();
 }
 

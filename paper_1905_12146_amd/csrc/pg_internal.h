@@ -124,6 +124,10 @@ struct EvalArgs {
     const int* eKind;                  // [MP] 0 real, 1 / 2 the two columns of a pair
     int expm_taylor;                   // 1: scaling and squaring (Q not usably diagonalisable)
     const void* Qop;                   // Q as MFMA A operands, three BF16 parts
+    const void* Q2op;                  // Q^2 likewise (Hessian)
+    // dense-state path: A fragments of Q and Q^2 of each rate matrix
+    // ([max(1, n_models)][2][DN_NF][64], the path's type)
+    const void* Qfrag;
 };
 
 enum Precision { FP64 = PG_FP64, FP32 = PG_FP32, SPLIT_BF16 = PG_SPLIT_BF16 };
@@ -135,6 +139,50 @@ enum Precision { FP64 = PG_FP64, FP32 = PG_FP32, SPLIT_BF16 = PG_SPLIT_BF16 };
 constexpr int MP = 64;
 constexpr size_t MF_SLOT_BYTES = 49152;
 constexpr size_t MF_QOP_BYTES = 3 * 8 * 64 * 16;
+
+// Dense-state path (FP64 / FP32 partials, 16 < M <= 32, e.g. 20 amino
+// acids): products on the matrix cores (16 x 16 x 4 MFMA), a vector of M
+// states x 16 patterns held as two 16-row blocks of the MFMA accumulator.
+// The accumulator's lane L = 16 g + c holds column c and, in its register
+// r, row 4 g + r (FP32) or g + 4 r (FP64): dn_b0_state.  Lane L holds
+// pattern c: in row block 0 the states dn_b0_state(g, r) (r < 4), in row
+// block 1 the states 16 + K1 g + r (r < K1, K1 = ceil((M - 16) / 4)); the
+// other rows of block 1 are padding.  A product A x runs KS = 4 + K1
+// k-steps per output block; at k-step s lane group k contributes the state
+// dn_col_state(s, k), which is the lane's own register s (block 0) or
+// s - 4 (block 1), so a product's output is the next product's input.  A
+// matrix is stored as dn_nf(M) = 2 KS fragments per lane, [ob][s][lane]:
+// entry A[dn_row_state(ob, L % 16)][dn_col_state(s, L / 16)] (0 for
+// padding).  `wide` selects the FP64 register order.
+constexpr bool dense_states(int M) { return M > 16 && M <= 32; }
+constexpr int dn_k1(int M) { return (M - 16 + 3) / 4; }
+constexpr int dn_ks(int M) { return 4 + dn_k1(M); }
+constexpr int dn_nf(int M) { return 2 * dn_ks(M); }
+// states as stored per pattern (M rounded up to a multiple of 4)
+constexpr int dn_md(int M) { return 16 + 4 * dn_k1(M); }
+constexpr int dn_b0_state(int g, int r, bool wide) { return wide ? g + 4 * r : 4 * g + r; }
+constexpr int dn_row_state(int M, int ob, int i, bool wide) {
+    // row i of block 1 is register r of lane group g
+    return ob == 0 ? i
+                   : ((wide ? i / 4 : i % 4) < dn_k1(M) &&
+                              16 + dn_k1(M) * (wide ? i % 4 : i / 4) + (wide ? i / 4 : i % 4) < M
+                          ? 16 + dn_k1(M) * (wide ? i % 4 : i / 4) + (wide ? i / 4 : i % 4)
+                          : -1);
+}
+constexpr int dn_col_state(int M, int s, int k, bool wide) {
+    return s < 4 ? dn_b0_state(k, s, wide)
+                 : (16 + dn_k1(M) * k + (s - 4) < M ? 16 + dn_k1(M) * k + (s - 4) : -1);
+}
+// entries (of the path's type) of one (branch, category) transition-matrix
+// slot: the fragments of P and of P^T (internal branch) or the tip table,
+// rows y < M = column y of P and row M = P 1, MD entries each in the lanes'
+// register order: entry 4 g + r is state dn_b0_state(g, r), entry 16 + j is
+// state 16 + j (tip branch)
+constexpr int dn_slot_elems(int M) {
+    return 2 * dn_nf(M) * 64 > (M + 1) * dn_md(M) ? 2 * dn_nf(M) * 64 : (M + 1) * dn_md(M);
+}
+// Q fragments then Q^2 fragments, per rate matrix
+constexpr int dn_qfrag_elems(int M) { return 2 * dn_nf(M) * 64; }
 
 // Kernel launchers (kernels.hip).  Each returns a hipError_t from the launch.
 bool kernel_supported(int M, int precision);
@@ -151,7 +199,11 @@ hipError_t launch_hsum(const EvalArgs& a, hipStream_t s);
 // split-BF16 launchers (kernels_mfma.hip)
 hipError_t launch_mfma_pmat(const EvalArgs& a, hipStream_t s);
 hipError_t launch_mfma_post(const EvalArgs& a, hipStream_t s);
-hipError_t launch_mfma_pre(const EvalArgs& a, hipStream_t s);
+hipError_t launch_mfma_pre(const EvalArgs& a, hipStream_t s, bool hess);
+// dense-state launchers (kernels_dense.hip)
+hipError_t launch_dense_pmat(const EvalArgs& a, int precision, hipStream_t s);
+hipError_t launch_dense_post(const EvalArgs& a, int precision, hipStream_t s);
+hipError_t launch_dense_pre(const EvalArgs& a, int precision, hipStream_t s, bool hess);
 size_t mfma_post_lds_bytes(const EvalArgs& a);
 size_t mfma_pre_lds_bytes(const EvalArgs& a);
 
@@ -173,6 +225,7 @@ int gsum_total_blocks(const EvalArgs& a);
 size_t post_lds_bytes(const EvalArgs& a, int precision);
 size_t pre_lds_bytes(const EvalArgs& a, int precision);
 hipError_t launch_batch(const BatchLaunch& b, hipStream_t s);
+hipError_t launch_dense_batch(const BatchLaunch& b, hipStream_t s);  // kernels_dense.hip
 
 // Q = V B V^-1 with B block diagonal (eigen.cpp).  kind[j]: 0 real
 // eigenvalue re[j]; 1 and 2 the two columns (real and imaginary part of the

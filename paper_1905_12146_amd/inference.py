@@ -10,7 +10,13 @@ Carlo on a random-effects clock).
   logL-and-gradient call, and a diagonal preconditioner from the Hessian
   diagonal (-d2/dtheta2 of the log posterior at a point, floored).
 * ``hmc(f, x0, ...)``: leapfrog HMC with a diagonal mass matrix (identity:
-  vanilla HMC; the preconditioner: preconditioned HMC).
+  vanilla HMC; a fixed preconditioner).
+* ``adaptive_hmc(f, neg_hess_diag, x0, ...)``: preconditioned HMC whose
+  diagonal mass matrix is the running average of -d2 log p / dx_i^2 over
+  the states visited every k-th iteration, clamped to [m_min, m_max]
+  (Section 3.2.1).
+* ``ess(x)``: effective sample size of a chain (initial monotone sequence
+  of autocorrelation pairs).
 * ``served_chains(server, ...)``: several HMC chains whose gradient calls go
   through the continuous-batching server, one session per chain.
 
@@ -93,14 +99,18 @@ class RandomEffectsClock:
         self.calls += 1
         return logL - 0.5 * float(theta @ theta) / self.sigma ** 2, g * t - theta / self.sigma ** 2
 
-    def precision_diag(self, theta: np.ndarray, floor: float = 1e-3) -> np.ndarray:
+    def neg_hess_diag(self, theta: np.ndarray) -> np.ndarray:
         """-d2 log p / dtheta_b^2 from the Hessian diagonal (Section 2.7):
         d2/dtheta2 logL(e^theta tau) = t^2 H_bb + t g_b."""
         t = self.lengths(theta)
         self.ctx.logL(t)
         g, h = self.ctx.hessian_diag()
-        prec = -(t * t * h + t * g) + 1.0 / self.sigma ** 2
-        return np.maximum(prec, floor)
+        self.calls += 1
+        return -(t * t * h + t * g) + 1.0 / self.sigma ** 2
+
+    def precision_diag(self, theta: np.ndarray, floor: float = 1e-3) -> np.ndarray:
+        """neg_hess_diag at one point, floored (a fixed preconditioner)."""
+        return np.maximum(self.neg_hess_diag(theta), floor)
 
 
 # ---------------------------------------------------------------- HMC
@@ -159,6 +169,80 @@ def hmc(f: Target, x0: np.ndarray, n_samples: int, step: float, n_leapfrog: int,
         lps[k] = lp
     return HMCResult(samples=out, log_p=lps, accept_rate=float(acc.mean()), energy_error=dH, n_grad=n_grad,
                      accepted=acc)
+
+
+def adaptive_hmc(f: Target, neg_hess_diag: Callable[[np.ndarray], np.ndarray], x0: np.ndarray, n_samples: int,
+                 step: float, n_leapfrog: int, k: int = 10, m_min: float = 1e-2, m_max: float = 1e4,
+                 seed: int = 0) -> HMCResult:
+    """HMC with the adaptive diagonal mass matrix of Section 3.2.1.
+
+    After every k-th iteration s, the negative Hessian diagonal of log p at
+    the current state joins a running average H^(s) (the mean over the
+    states x^(k), x^(2k), ..., x^(s)); the following iterations use
+    M_ii = min(max(H_ii^(s), m_min), m_max).  Until the first update the
+    mass matrix is the identity.  The change of H between updates is
+    O(1/s) (vanishing adaptation).  The result's ``mass_history`` holds the
+    mass matrix after each update."""
+    rng = np.random.default_rng(seed)
+    x = np.asarray(x0, dtype=np.float64).copy()
+    d = x.size
+    mass = np.ones(d)
+    h_sum = np.zeros(d)
+    n_upd = 0
+    lp, g = f(x)
+    n_grad = 1
+    out = np.empty((n_samples, d))
+    lps = np.empty(n_samples)
+    dH = np.empty(n_samples)
+    acc = np.zeros(n_samples, dtype=bool)
+    history = []
+    for it in range(n_samples):
+        inv_mass = 1.0 / mass
+        p0 = rng.normal(size=d) * np.sqrt(mass)
+        H0 = -lp + 0.5 * float(p0 @ (inv_mass * p0))
+        x1, p1, lp1, g1 = leapfrog(f, x, p0, g, step, n_leapfrog, inv_mass)
+        n_grad += n_leapfrog
+        H1 = -lp1 + 0.5 * float(p1 @ (inv_mass * p1)) if np.isfinite(lp1) else np.inf
+        dH[it] = H1 - H0
+        if np.log(rng.uniform()) < -(H1 - H0):
+            x, lp, g = x1, lp1, g1
+            acc[it] = True
+        out[it] = x
+        lps[it] = lp
+        if (it + 1) % k == 0:
+            h_sum += neg_hess_diag(x)
+            n_upd += 1
+            mass = np.clip(h_sum / n_upd, m_min, m_max)
+            history.append(mass.copy())
+    r = HMCResult(samples=out, log_p=lps, accept_rate=float(acc.mean()), energy_error=dH, n_grad=n_grad,
+                  accepted=acc)
+    r.mass_history = np.array(history)
+    return r
+
+
+def ess(x: np.ndarray) -> float:
+    """Effective sample size of one chain x[n]: n / (1 + 2 sum_t rho_t), the
+    autocorrelation sum truncated by Geyer's initial monotone sequence (sums
+    of adjacent pairs, kept while positive and made non-increasing)."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.size
+    if n < 4:
+        return float(n)
+    xc = x - x.mean()
+    var = float(xc @ xc) / n
+    if var == 0.0:
+        return float(n)
+    f = np.fft.rfft(xc, 2 * n)
+    acov = np.fft.irfft(f * np.conj(f))[:n] / n
+    rho = acov / var
+    pairs = []
+    for t in range(0, n - 1, 2):
+        gsum = rho[t] + rho[t + 1]
+        if gsum <= 0.0:
+            break
+        pairs.append(min(gsum, pairs[-1]) if pairs else gsum)
+    tau = -1.0 + 2.0 * float(np.sum(pairs)) if pairs else 1.0
+    return float(n / max(tau, 1e-12))
 
 
 # ---------------------------------------------------------------- chains through the server

@@ -156,7 +156,9 @@ def test_failed_upload_wakes_waiting_caller(gpu):
         waiter.join(timeout=60)
         assert not waiter.is_alive(), "the waiting caller was not woken"
         assert out["r"][0] == B.PG_E_OOM, out
-        srv.close(sid)
+        with pytest.raises(B.PhyloGradError) as e:   # the server closed it
+            srv.close(sid)
+        assert e.value.code == B.PG_E_STATE
         ok = srv.open(small_w)                 # the server keeps serving
         st, _, _, _ = srv.wait(srv.submit(ok, small_w.t), len(small_w.t))
         assert st == B.PG_OK

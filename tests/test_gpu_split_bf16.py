@@ -120,13 +120,24 @@ def test_logl_only_then_grad(gpu):
 
 
 def test_unsupported_calls(gpu):
-    w = small(n_tips=6, n_patterns=20, n_states=61)
-    with B.Context(0, B.PG_SPLIT_BF16) as ctx:
-        ctx.set_workload(w)
-        ctx.logL(w.t)
-        with pytest.raises(B.PhyloGradError) as e:
-            ctx.hessian_diag()
-        assert e.value.code == B.PG_E_UNSUPPORTED
     with pytest.raises(B.PhyloGradError) as e:
         B.pg_server_create(0, B.PG_SPLIT_BF16, 1 << 30, 4)
     assert e.value.code == B.PG_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n_tips,n_cats,n_states", [(7, 2, 61), (20, 3, 4), (12, 4, 20)])
+def test_hessian_split(gpu, n_tips, n_cats, n_states):
+    """Section 2.7 on the split-BF16 path: Q^2 m split in three BF16 parts;
+    within 1e-5 of the FP64 oracle with the cancellation-free scale
+    sum_s w_s (|d2L_s/L_s| + (dL_s/L_s)^2)."""
+    w = small(n_tips=n_tips, n_cats=n_cats, n_states=n_states, n_patterns=37, seed=60 + n_tips,
+              ambiguous=0.05, mean_t=0.15)
+    with B.Context(0, B.PG_SPLIT_BF16) as ctx:
+        ctx.set_workload(w)
+        logL, grad = ctx.logL_and_grad(w.t)
+        g2, h = ctx.hessian_diag()
+    assert np.array_equal(grad, g2)
+    nh = O.naive_hessian_diag(*args_of(w))
+    rel = np.abs(h - nh["hess"]) / np.maximum(nh["abs_hess"], np.finfo(float).tiny)
+    print("split Hessian", n_states, "A-rule max", rel.max(), flush=True)
+    assert (rel <= TOL).all(), rel.max()

@@ -331,6 +331,66 @@ def update_bench(args):
                       "speedup": round(full_us / upd_us, 2), "calls": n}), flush=True)
 
 
+def hmc_bench(args):
+    """Vanilla HMC against HMC with the adaptive Hessian-informed diagonal
+    mass matrix (Section 3.2.1) on a random-effects clock (log rate of every
+    branch, t_b = exp(theta_b) tau_b, theta_b ~ N(0, 0.5^2)), with the
+    gradient and the Hessian diagonal from the GPU.  Each sampler tunes its
+    step size for about 70% acceptance in a warm-up, then runs the same
+    number of iterations; ESS per second (min and median over the branches)
+    is reported for both.  Prints one JSON line."""
+    from paper_1905_12146_amd import binding as B
+    from paper_1905_12146_amd.inference import RandomEffectsClock, adaptive_hmc, ess, hmc
+    from synth import make_workload
+
+    w = make_workload("C5", n_states=4, n_tips=args.hmc_tips, n_patterns=1000)
+    ctx = B.Context(0, B.PG_FP64)
+    ctx.set_workload(w)
+    model = RandomEffectsClock(ctx, w.tau.copy(), sigma=0.5)
+    d = len(w.t)
+    n_leap, n_warm, n_iter = 10, args.hmc_warmup, args.hmc_iters
+
+    def run(kind, seed):
+        x, step = np.zeros(d), 0.02
+        state = {"mass": np.ones(d), "h_sum": np.zeros(d), "n": 0}
+        # warm-up in blocks of 10 iterations: adjust the step towards 70%
+        # acceptance (pHMC also adapts its mass matrix meanwhile)
+        t0 = time.perf_counter()
+        for blk in range(n_warm // 10):
+            if kind == "vhmc":
+                r = hmc(model, x, 10, step, n_leap, seed=seed + blk)
+            else:
+                r = adaptive_hmc(model, model.neg_hess_diag, x, 10, step, n_leap, k=10, seed=seed + blk,
+                                 init=(state["h_sum"], state["n"]))
+                state["h_sum"], state["n"] = r.h_sum, r.n_updates
+            x = r.samples[-1]
+            step *= float(np.exp(0.5 * (r.accept_rate - 0.7)))
+        t_warm = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        if kind == "vhmc":
+            r = hmc(model, x, n_iter, step, n_leap, seed=seed + 999)
+        else:
+            r = adaptive_hmc(model, model.neg_hess_diag, x, n_iter, step, n_leap, k=10, seed=seed + 999,
+                             init=(state["h_sum"], state["n"]))
+        el = time.perf_counter() - t0
+        e = np.array([ess(r.samples[:, i]) for i in range(d)])
+        return {"step": round(step, 5), "accept": round(r.accept_rate, 3), "seconds": round(el, 2),
+                "warmup_seconds": round(t_warm, 2), "ess_min": round(float(e.min()), 1),
+                "ess_median": round(float(np.median(e)), 1), "ess_per_s_min": round(float(e.min()) / el, 2),
+                "ess_per_s_median": round(float(np.median(e)) / el, 2)}
+
+    v = run("vhmc", 100)
+    ph = run("phmc", 200)
+    ctx.close()
+    print(json.dumps({"metric": "ESS/s of HMC on a random-effects clock: vanilla vs adaptive preconditioned",
+                      "workload": f"Yule N={w.n_tips}, 4-state, K=4, S=1000 simulated, {d} branch rates, "
+                                  f"{n_leap} leapfrog steps, {n_iter} iterations after {n_warm} warm-up",
+                      "vhmc": v, "phmc": ph,
+                      "speedup_min": round(ph["ess_per_s_min"] / max(v["ess_per_s_min"], 1e-12), 2),
+                      "speedup_median": round(ph["ess_per_s_median"] / max(v["ess_per_s_median"], 1e-12), 2)}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -358,6 +418,11 @@ def main():
                     help="HBM budget of the extra run in which admission binds")
     ap.add_argument("--budget-gb", type=float, default=32.0)
     ap.add_argument("--max-sessions", type=int, default=64)
+    ap.add_argument("--hmc", action="store_true",
+                    help="ESS/s of vanilla vs adaptive preconditioned HMC on a random-effects clock")
+    ap.add_argument("--hmc-tips", type=int, default=150)
+    ap.add_argument("--hmc-iters", type=int, default=1500)
+    ap.add_argument("--hmc-warmup", type=int, default=300)
     ap.add_argument("--updates", action="store_true",
                     help="partial re-evaluation: single-branch logL updates against full logL (C2)")
     args = ap.parse_args()
@@ -369,6 +434,9 @@ def main():
         return
     if args.updates:
         update_bench(args)
+        return
+    if args.hmc:
+        hmc_bench(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -480,6 +548,21 @@ def main():
         tf = fl / (avg_ms[dom] * 1e-3) / 1e12 if avg_ms[dom] > 0 else 0.0
         roofline["mfma"] = {"kernel": dom, "bf16_flops_per_launch": fl, "achieved": round(tf, 2),
                             "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tf / 2500.0, 4)}
+
+    if m == 20 and prec != B.PG_SPLIT_BF16:
+        # executed matrix-core work of the dense-state kernels: 16x16x4 MFMAs
+        # (2048 flops each, FP64 or FP32) per tile; a 20 x 20 product is 2
+        # row blocks x 5 k-steps = 10 MFMAs (62.5% of the issued work is the
+        # 20 x 20 product itself); post: one per internal non-root node (P p),
+        # pre: one per child (Q m) plus one per internal child (P^T u)
+        n_tiles = K * ((S + 15) // 16)
+        n_int = N - 2
+        mf = {"post": 10 * n_int, "pre": 10 * (2 * N - 2) + 10 * n_int}
+        peak = 78.6 if prec == B.PG_FP64 else 157.3
+        fl = mf[dom] * n_tiles * 2048
+        tf = fl / (avg_ms[dom] * 1e-3) / 1e12 if avg_ms[dom] > 0 else 0.0
+        roofline["mfma"] = {"kernel": dom, "flops_per_launch": fl, "achieved": round(tf, 2),
+                            "peak": peak, "unit": "TFLOP/s", "frac": round(tf / peak, 4)}
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "evals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),

@@ -257,15 +257,17 @@ int64_t pg_device_bytes(const pg_ctx* ctx);
 int64_t pg_footprint_bytes(int32_t n_tips, int32_t n_patterns, int32_t n_states,
                            int32_t n_cats, int precision);
 
-/* The eigen-decomposition pg_set_model computes for a PG_SPLIT_BF16
- * context (host only, no device needed): Q = V B V^-1 with B block diagonal,
- * 1x1 blocks re[j] for real eigenvalues (kind[j] = 0) and, for a conjugate
+/* The eigen-decomposition pg_set_model computes for a PG_SPLIT_BF16 or a
+ * 20-state context (host only, no device needed): Q = V B V^-1 with B block
+ * diagonal, 1x1 blocks re[j] for real eigenvalues (kind[j] = 0) and, for a conjugate
  * pair re +- i im, the 2x2 block [[re, im], [-im, re]] on columns j, j+1
  * (kind 1, 2) that hold the real and imaginary parts of the eigenvector of
  * re + i im.  V, Vinv: m x m row-major (caller-allocated, like re, im,
  * kind[m]); cond = ||V||_1 ||V^-1||_1; resid = max|V B V^-1 - Q| / max|Q|.
- * The split-BF16 kernels use it when cond <= 1e6 and resid <= 1e-11, and
- * scaling and squaring otherwise.  PG_E_MODEL when no decomposition was
+ * The split-BF16 kernels use it when cond <= 1e6 and resid <= 1e-11, the
+ * 20-state FP64 kernels when cond <= 1e4 and resid <= 1e-13 (FP32: as
+ * split-BF16), each with a homogeneous model, and scaling and squaring
+ * otherwise.  PG_E_MODEL when no decomposition was
  * found (e.g. the QR iteration did not converge). */
 int pg_eigensystem(int32_t m, const double* Q, double* V, double* Vinv, double* re, double* im,
                    int32_t* kind, double* cond, double* resid);

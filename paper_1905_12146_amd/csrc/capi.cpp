@@ -242,6 +242,33 @@ void prepare_split_model(pg_ctx* c) {
     operands(c->Q2, c->Q2op);
 }
 
+// Dense-state path: an eigen-decomposition of Q (m x m) for the transition
+// matrices F = P - I = V (exp(B rate t) - I) V^-1, used when it is well
+// conditioned enough for the precision (FP64: cond_1(V) <= 1e4 and a
+// reconstruction error <= 1e-13, about 1e-12 relative in F; FP32: 1e6 and
+// 1e-11); otherwise the kernels use scaling and squaring.
+void prepare_dense_model(pg_ctx* c) {
+    const int m = c->m;
+    EigenSystem es;
+    const bool ok = eigen_decompose(m, c->Q.data(), es);
+    const bool wide = c->precision == PG_FP64;
+    c->expm_taylor = !(ok && es.cond <= (wide ? 1e4 : 1e6) && es.resid <= (wide ? 1e-13 : 1e-11));
+    c->eig_cond = ok ? es.cond : INFINITY;
+    c->eig_resid = ok ? es.resid : INFINITY;
+    c->eV.assign((size_t)m * m, 0.0);
+    c->eVinv.assign((size_t)m * m, 0.0);
+    c->eRe.assign(m, 0.0);
+    c->eIm.assign(m, 0.0);
+    c->eKind.assign(m, 0);
+    if (!c->expm_taylor) {
+        c->eV = es.V;
+        c->eVinv = es.Vinv;
+        c->eRe = es.re;
+        c->eIm = es.im;
+        c->eKind = es.kind;
+    }
+}
+
 int check_tree(pg_ctx* c, int32_t N, const int32_t* parent) {
     const int n_nodes = 2 * N - 1;
     const int root = n_nodes - 1;
@@ -344,6 +371,13 @@ std::vector<BufSpec> buffer_specs(const Dims& d, bool lean) {
         add("eKind", sizeof(int) * MP);
         add("Qop", MF_QOP_BYTES);
         add("Q2op", MF_QOP_BYTES);
+    }
+    if (dense) {
+        add("eV", sizeof(double) * M * M);
+        add("eVinv", sizeof(double) * M * M);
+        add("eRe", sizeof(double) * M);
+        add("eIm", sizeof(double) * M);
+        add("eKind", sizeof(int) * M);
     }
     add("msg", es * vec * (N - 1));
     add("qv", es * vec * (N - 1));
@@ -485,7 +519,7 @@ void fill_args(const pg_ctx* c, At&& at, EvalArgs& a) {
         a.qnorm_m = static_cast<const double*>(at("bm_qnorm"));
         a.branch_model = static_cast<const int*>(at("bm_model"));
     }
-    if (split) {
+    if (split || (dense_states(M) && c->precision != PG_SPLIT_BF16)) {
         a.eV = static_cast<const double*>(at("eV"));
         a.eVinv = static_cast<const double*>(at("eVinv"));
         a.eRe = static_cast<const double*>(at("eRe"));
@@ -996,6 +1030,7 @@ int pg_set_model(pg_ctx* c, int32_t m, const double* Q, const double* pi, int32_
         c->catw.assign(catw, catw + K);
         c->qnorm = qnorm;
         if (c->precision == PG_SPLIT_BF16) prepare_split_model(c);
+        else if (dense_states(m)) prepare_dense_model(c);
         if (old_m != m) c->bm_n = 0;  // branch models have the old state count
         c->model_set = true;
         c->dev_stale = true;

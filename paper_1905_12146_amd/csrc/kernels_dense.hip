@@ -22,11 +22,12 @@
 // column y, the message of an observed state y; row m: P 1, the message of
 // missing data).  Q and Q^2 fragments come from the host.
 //
-// Work decomposition as the split-BF16 kernels: a workgroup of DW waves owns
+// Work decomposition as the split-BF16 kernels: a workgroup of waves owns
 // one tile and walks the tree level by level (nodes of one height are
-// independent; a barrier separates levels), one node per wave at a time,
-// the next node's loads issued before the current node's arithmetic; tiles
-// are mapped to workgroups XCD by XCD.
+// independent; a barrier separates levels), one node per wave at a time;
+// the post-order pass issues the next node's loads before the current
+// node's arithmetic, the pre-order pass (more registers per wave) does not.
+// Tiles are mapped to workgroups XCD by XCD.
 #include <type_traits>
 
 #include "device_common.h"
@@ -42,8 +43,10 @@ using v4 = typename std::conditional<sizeof(T) == 8, d4, f4>::type;
 __device__ inline d4 mma(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 __device__ inline f4 mma(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
-constexpr int DW = 8;  // waves per traversal workgroup
-constexpr int DN_THREADS = DW * 64;
+// waves per traversal workgroup: the post-order kernel runs more, smaller
+// workgroups (its FP64 variant holds fewer registers and keeps three
+// workgroups of four waves per CU); the pre-order kernel eight
+constexpr int DW_POST = 4, DW_PRE = 8;
 
 // The lane's M states of its pattern: row block 0 and the K1 rows of block 1.
 template <int M, typename T>
@@ -235,10 +238,13 @@ template <int M, typename T>
 __device__ inline void dense_pmat_body(const EvalArgs& a, int block) {
     constexpr int NF = dn_nf(M), KS = dn_ks(M), MD = dn_md(M);
     constexpr bool wide = sizeof(T) == 8;
-    __shared__ double A[M * M], G[M * M], W[M * M];
+    __shared__ double A[M * M], G[M * M], W[M * M], fc[M], fs[M];
     const int b = a.blist ? a.blist[block / a.K] : block / a.K, l = block % a.K;
     T* slot = static_cast<T*>(a.P) + ((size_t)b * a.K + l) * dn_slot_elems(M);
-    const bool ok = taylor_F_lds<M>(a, b, l, A, G, W);
+    // eigen route when the host found Q usably diagonalisable (homogeneous
+    // model), scaling and squaring otherwise
+    const bool ok = (!a.expm_taylor && a.n_models == 0) ? eigen_F_lds<M>(a, b, l, A, G, W, fc, fs)
+                                                         : taylor_F_lds<M>(a, b, l, A, G, W);
     // W = F, P = I + F
     auto pent = [&](int x, int y) { return ((x == y) ? 1.0 : 0.0) + W[x * M + y]; };
     if (b >= a.n_tips) {
@@ -340,7 +346,7 @@ __device__ inline void dense_post_body(const EvalArgs& a, int tile, int4* lds_sc
             dchild_issue<M, T>(a, nd.y, tile, s, lane, ci);
             dchild_issue<M, T>(a, nd.z, tile, s, lane, cj);
             while (true) {
-                const int nidx = idx + DW;
+                const int nidx = idx + DW_POST;
                 const bool more = nidx < end;
                 int4 nn = nd;
                 DChild<M, T> ni, nj;
@@ -359,12 +365,12 @@ __device__ inline void dense_post_body(const EvalArgs& a, int tile, int4* lds_sc
         }
         __syncthreads();
     }
-    __shared__ int red[DW][TP];
+    __shared__ int red[DW_POST][TP];
     if (g == 0) red[wv][ps] = esum;
     __syncthreads();
     if (wv == 0 && g == 0) {
         int tot = 0;
-        for (int i = 0; i < DW; ++i) tot += red[i][ps];
+        for (int i = 0; i < DW_POST; ++i) tot += red[i][ps];
         if (a.expo_delta) a.rootE[(size_t)l * a.S_pad + s] += tot;
         else a.rootE[(size_t)l * a.S_pad + s] = tot;
     }
@@ -382,8 +388,8 @@ __device__ inline void dense_post_body(const EvalArgs& a, int tile, int4* lds_sc
 
 template <int M, typename T, bool HESS, bool NH>
 __device__ inline void dense_pre_child(const EvalArgs& a, int c, int l, int tile, int s, int lane, const Coef& cf,
-                                       const DV<M, T>& u, const DV<M, T>& mown, const T qf[dn_nf(M)],
-                                       const T q2f[dn_nf(M)], const T pf[dn_nf(M)]) {
+                                       const DV<M, T>& u, const DV<M, T>& mown, const T* qf,
+                                       const T* q2f, const T pf[dn_nf(M)]) {
     constexpr int NF = dn_nf(M);
     const int g = lane >> 4;
     T den = ddot(u, mown);
@@ -403,11 +409,14 @@ __device__ inline void dense_pre_child(const EvalArgs& a, int c, int l, int tile
             num2 = ddot(u, q2m);
         }
     } else {
-        dprod<M, T>(qf, mown, qm);
+        T f[NF];
+        frags_load<M, T>(qf, lane, f);
+        dprod<M, T>(f, mown, qm);
         num = ddot(u, qm);
         if constexpr (HESS) {
+            frags_load<M, T>(q2f, lane, f);
             DV<M, T> q2m;
-            dprod<M, T>(q2f, mown, q2m);
+            dprod<M, T>(f, mown, q2m);
             num2 = ddot(u, q2m);
         }
     }
@@ -463,13 +472,16 @@ __device__ inline void dense_pre_body(const EvalArgs& a, int tile, int4* lds_sch
         // the category-0 tile of each pattern block also forms its logL part
         if (l == 0 && wv == 0 && g == 0) logl_block_part(a, pb, ps, r);
     }
-    // Q (and Q^2) fragments of the homogeneous model stay in registers
-    T qf[NF], q2f[NF];
+    // Q (and Q^2) fragments of the homogeneous model are staged in LDS; each
+    // product reloads them (in registers they would cost a wave per SIMD)
+    __shared__ T qsh[2 * NF * 64];
     if constexpr (!NH) {
         const T* QF = static_cast<const T*>(a.Qfrag);
-        frags_load<M, T>(QF, lane, qf);
-        if constexpr (HESS) frags_load<M, T>(QF + NF * 64, lane, q2f);
+        for (int i = threadIdx.x; i < (HESS ? 2 : 1) * NF * 64; i += blockDim.x) qsh[i] = QF[i];
+        __syncthreads();
     }
+    const T* qf = qsh;
+    const T* q2f = qsh + NF * 64;
     stage_schedule(a, lds_sched);
     for (int h = a.n_levels - 1; h >= 0; --h) {
         const int end = a.level_off[h + 1];
@@ -479,14 +491,10 @@ __device__ inline void dense_pre_body(const EvalArgs& a, int tile, int4* lds_sch
             DPreLd<M, T> cur;
             dpre_issue<M, T>(a, nd, tile, s, lane, cur);
             while (true) {
-                const int nidx = idx + DW;
+                const int nidx = idx + DW_PRE;
                 const bool more = nidx < end;
                 int4 nn = nd;
-                DPreLd<M, T> nxt;
-                if (more) {
-                    nn = sched_at(a, lds_sched, nidx);
-                    dpre_issue<M, T>(a, nn, tile, s, lane, nxt);
-                }
+                if (more) nn = sched_at(a, lds_sched, nidx);
                 T pf[NF];
                 if (nd.y >= a.n_tips) frags_load<M, T>(dslot<M, T>(a, nd.y, l) + NF * 64, lane, pf);
                 DV<M, T> q;
@@ -501,7 +509,7 @@ __device__ inline void dense_pre_body(const EvalArgs& a, int tile, int4* lds_sch
                 dense_pre_child<M, T, HESS, NH>(a, nd.z, l, tile, s, lane, cf, uj, mj, qf, q2f, pf);
                 if (!more) break;
                 nd = nn;
-                cur = nxt;
+                dpre_issue<M, T>(a, nd, tile, s, lane, cur);
                 idx = nidx;
             }
         }
@@ -524,14 +532,14 @@ __global__ void __launch_bounds__(256) dense_pmat_batch(const EvalArgs* __restri
 }
 
 template <int M, typename T>
-__global__ void __launch_bounds__(DN_THREADS) dense_post_kernel(EvalArgs a) {
+__global__ void __launch_bounds__(DW_POST * 64) dense_post_kernel(EvalArgs a) {
     extern __shared__ int4 lds_dyn[];
     const int tile = xcd_tile(blockIdx.x, a.n_tiles);
     if (tile >= a.n_tiles) return;
     dense_post_body<M, T>(a, tile, lds_dyn);
 }
 template <int M, typename T>
-__global__ void __launch_bounds__(DN_THREADS) dense_post_batch(const EvalArgs* __restrict__ reqs,
+__global__ void __launch_bounds__(DW_POST * 64) dense_post_batch(const EvalArgs* __restrict__ reqs,
                                                                 const int2* __restrict__ map) {
     extern __shared__ int4 lds_dyn[];
     const int2 m = map[blockIdx.x];
@@ -539,14 +547,14 @@ __global__ void __launch_bounds__(DN_THREADS) dense_post_batch(const EvalArgs* _
 }
 
 template <int M, typename T, bool HESS, bool NH>
-__global__ void __launch_bounds__(DN_THREADS) dense_pre_kernel(EvalArgs a) {
+__global__ void __launch_bounds__(DW_PRE * 64) dense_pre_kernel(EvalArgs a) {
     extern __shared__ int4 lds_dyn[];
     const int tile = xcd_tile(blockIdx.x, a.n_tiles);
     if (tile >= a.n_tiles) return;
     dense_pre_body<M, T, HESS, NH>(a, tile, lds_dyn);
 }
 template <int M, typename T>
-__global__ void __launch_bounds__(DN_THREADS) dense_pre_batch(const EvalArgs* __restrict__ reqs,
+__global__ void __launch_bounds__(DW_PRE * 64) dense_pre_batch(const EvalArgs* __restrict__ reqs,
                                                                const int2* __restrict__ map) {
     extern __shared__ int4 lds_dyn[];
     const int2 m = map[blockIdx.x];
@@ -562,12 +570,12 @@ static hipError_t dpmat(const EvalArgs& a, hipStream_t st) {
 }
 template <int M, typename T>
 static hipError_t dpost(const EvalArgs& a, hipStream_t st) {
-    dense_post_kernel<M, T><<<N_XCD * xcd_per(a.n_tiles), DN_THREADS, sched_lds_bytes(a), st>>>(a);
+    dense_post_kernel<M, T><<<N_XCD * xcd_per(a.n_tiles), DW_POST * 64, sched_lds_bytes(a), st>>>(a);
     return hipGetLastError();
 }
 template <int M, typename T>
 static hipError_t dpre(const EvalArgs& a, hipStream_t st, bool hess) {
-    const dim3 grid(N_XCD * xcd_per(a.n_tiles)), block(DN_THREADS);
+    const dim3 grid(N_XCD * xcd_per(a.n_tiles)), block(DW_PRE * 64);
     const size_t lds = sched_lds_bytes(a);
     if (a.n_models) {
         if (hess) dense_pre_kernel<M, T, true, true><<<grid, block, lds, st>>>(a);
@@ -581,8 +589,8 @@ static hipError_t dpre(const EvalArgs& a, hipStream_t st, bool hess) {
 template <int M, typename T>
 static hipError_t dbatch(const BatchLaunch& b, hipStream_t st) {
     if (b.pmat_blocks > 0) dense_pmat_batch<M, T><<<b.pmat_blocks, 256, 0, st>>>(b.reqs, b.pmat_map);
-    dense_post_batch<M, T><<<b.trav_blocks, DN_THREADS, b.post_lds, st>>>(b.reqs, b.trav_map);
-    dense_pre_batch<M, T><<<b.trav_blocks, DN_THREADS, b.pre_lds, st>>>(b.reqs, b.trav_map);
+    dense_post_batch<M, T><<<b.trav_blocks, DW_POST * 64, b.post_lds, st>>>(b.reqs, b.trav_map);
+    dense_pre_batch<M, T><<<b.trav_blocks, DW_PRE * 64, b.pre_lds, st>>>(b.reqs, b.trav_map);
     return hipGetLastError();
 }
 

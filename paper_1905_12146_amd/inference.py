@@ -173,7 +173,7 @@ def hmc(f: Target, x0: np.ndarray, n_samples: int, step: float, n_leapfrog: int,
 
 def adaptive_hmc(f: Target, neg_hess_diag: Callable[[np.ndarray], np.ndarray], x0: np.ndarray, n_samples: int,
                  step: float, n_leapfrog: int, k: int = 10, m_min: float = 1e-2, m_max: float = 1e4,
-                 seed: int = 0) -> HMCResult:
+                 seed: int = 0, init: Optional[Tuple[np.ndarray, int]] = None) -> HMCResult:
     """HMC with the adaptive diagonal mass matrix of Section 3.2.1.
 
     After every k-th iteration s, the negative Hessian diagonal of log p at
@@ -182,13 +182,15 @@ def adaptive_hmc(f: Target, neg_hess_diag: Callable[[np.ndarray], np.ndarray], x
     M_ii = min(max(H_ii^(s), m_min), m_max).  Until the first update the
     mass matrix is the identity.  The change of H between updates is
     O(1/s) (vanishing adaptation).  The result's ``mass_history`` holds the
-    mass matrix after each update."""
+    mass matrix after each update; ``h_sum`` and ``n_updates`` the running
+    sum and count, which ``init`` takes to continue an earlier run's
+    adaptation."""
     rng = np.random.default_rng(seed)
     x = np.asarray(x0, dtype=np.float64).copy()
     d = x.size
-    mass = np.ones(d)
-    h_sum = np.zeros(d)
-    n_upd = 0
+    h_sum = np.zeros(d) if init is None else np.asarray(init[0], dtype=np.float64).copy()
+    n_upd = 0 if init is None else int(init[1])
+    mass = np.clip(h_sum / n_upd, m_min, m_max) if n_upd else np.ones(d)
     lp, g = f(x)
     n_grad = 1
     out = np.empty((n_samples, d))
@@ -217,6 +219,7 @@ def adaptive_hmc(f: Target, neg_hess_diag: Callable[[np.ndarray], np.ndarray], x
     r = HMCResult(samples=out, log_p=lps, accept_rate=float(acc.mean()), energy_error=dH, n_grad=n_grad,
                   accepted=acc)
     r.mass_history = np.array(history)
+    r.h_sum, r.n_updates = h_sum, n_upd
     return r
 
 

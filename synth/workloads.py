@@ -321,7 +321,7 @@ def make_workload(name: str, seed: Optional[int] = None, **overrides) -> Workloa
     n, m, K, S = cfg["n_tips"], cfg["n_states"], cfg["n_cats"], cfg["n_patterns"]
     parent = yule_tree(n, rng)
     tau = log_r = None
-    if name == "C5" and m == 20 and cfg.get("clock", True):
+    if name == "C5" and cfg.get("clock", True):
         tau = rng.exponential(cfg["mean_t"], size=2 * n - 2)
         log_r = rng.normal(0.0, 0.5, size=2 * n - 2)
         t = np.exp(log_r) * tau

@@ -102,3 +102,37 @@ def test_hessian_fp32(gpu):
     rel = np.abs(h - nh["hess"]) / np.maximum(nh["abs_hess"], np.finfo(float).tiny)
     print("dense FP32 Hessian, A rule max", rel.max(), flush=True)
     assert (rel <= 1e-5).all()
+
+
+def _chain_q(m):
+    """A defective generator (one Jordan block): x -> x + 1 at rate 1, the
+    last state absorbing.  No eigen-decomposition exists, so the transition
+    matrices come from scaling and squaring."""
+    Q = np.zeros((m, m))
+    for x in range(m - 1):
+        Q[x, x] = -1.0
+        Q[x, x + 1] = 1.0
+    return Q
+
+
+def test_eigen_route_and_its_fallbacks(gpu):
+    """Transition matrices by the eigen-decomposition of Q (a random Q, and
+    Jukes-Cantor with a 19-fold eigenvalue) and by scaling and squaring (a
+    defective Q), each against the oracle (which uses SciPy's expm)."""
+    from tests._fixtures import jc_matrix
+    from synth.workloads import simulate_sites
+    for label, Q in (("random", None), ("jukes-cantor", jc_matrix(20)), ("defective", _chain_q(20))):
+        w = small(n_tips=25, n_patterns=40, n_cats=2, n_states=20, seed=71, ambiguous=0.05, mean_t=0.2)
+        if Q is not None:
+            w.Q = Q
+        if label == "defective":
+            # uniform tips can need a jump over most of the chain on one short
+            # branch, which the truncated series prices at exactly zero; tips
+            # simulated under the chain itself keep every pattern likely
+            rng = np.random.Generator(np.random.PCG64(72))
+            w.tip_states = simulate_sites(w.parent, w.t, Q, w.pi, w.rates, w.cat_weights, 40, rng)
+        m = 20
+        V, Vinv, re, im, kind, cond, resid = B.pg_eigensystem(w.Q) if label != "defective" else (None,) * 7
+        print("dense eigen route", label, cond, resid, flush=True)
+        for precision in (B.PG_FP64, B.PG_FP32):
+            check(w, precision)

@@ -9,8 +9,8 @@ import pytest
 
 import oracle as O
 from paper_1905_12146_amd import binding as B
-from paper_1905_12146_amd.inference import (RandomEffectsClock, hmc, lbfgs_maximize, leapfrog,
-                                            mle_branch_lengths, served_chains)
+from paper_1905_12146_amd.inference import (RandomEffectsClock, adaptive_hmc, hmc, lbfgs_maximize,
+                                            leapfrog, mle_branch_lengths, served_chains)
 from tests._fixtures import args_of, small
 
 pytestmark = pytest.mark.gpu
@@ -71,3 +71,50 @@ def test_served_chains_equal_direct_chains(gpu):
             rd = hmc(RandomEffectsClock(ctx, tau, 0.5), np.zeros(len(tau)), 6, 0.02, 5, seed=seed)
         assert np.array_equal(rs.samples, rd.samples) and np.array_equal(rs.log_p, rd.log_p)
     assert stats["calls"] == 3 * (1 + 6 * 5)
+
+
+
+class _OracleCtx:
+    """logL_and_grad / logL / hessian_diag of a workload from the CPU oracle."""
+
+    def __init__(self, w):
+        self.args = list(args_of(w))
+        self.t = None
+
+    def logL_and_grad(self, t):
+        self.args[1] = np.asarray(t, dtype=np.float64)
+        r = O.linear_gradient(*self.args)
+        return r["logL"], r["grad"]
+
+    def logL(self, t):
+        self.t = np.asarray(t, dtype=np.float64)
+        return self.logL_and_grad(t)[0]
+
+    def hessian_diag(self):
+        self.args[1] = self.t
+        r = O.linear_gradient(*self.args)
+        return r["grad"], r["hess"]
+
+
+def test_hmc_with_gpu_gradients_follows_the_oracle_driven_chain(gpu):
+    """Same seed, same model: vanilla HMC and adaptive pHMC (Section 3.2.1,
+    mass matrix from the GPU Hessian diagonal) driven by the GPU path take the
+    same accept decisions and the same states as when driven by the oracle's
+    gradient and Hessian, to rounding."""
+    w = _work(n=10, s=120, k=2, seed=8)
+    oracle_model = RandomEffectsClock(_OracleCtx(w), w.t.copy(), sigma=0.5)
+    theta0 = np.zeros(len(w.t))
+    with B.Context(0, B.PG_FP64) as ctx:
+        ctx.set_workload(w)
+        gpu_model = RandomEffectsClock(ctx, w.t.copy(), sigma=0.5)
+        rv = hmc(gpu_model, theta0, 12, step=0.02, n_leapfrog=6, seed=11)
+        ra = adaptive_hmc(gpu_model, gpu_model.neg_hess_diag, theta0, 12, step=0.05, n_leapfrog=6, k=3,
+                          m_min=1e-2, m_max=1e4, seed=12)
+    ov = hmc(oracle_model, theta0, 12, step=0.02, n_leapfrog=6, seed=11)
+    oa = adaptive_hmc(oracle_model, oracle_model.neg_hess_diag, theta0, 12, step=0.05, n_leapfrog=6, k=3,
+                      m_min=1e-2, m_max=1e4, seed=12)
+    print("vHMC accepted", rv.accepted.sum(), "pHMC accepted", ra.accepted.sum(), flush=True)
+    assert np.array_equal(rv.accepted, ov.accepted) and np.array_equal(ra.accepted, oa.accepted)
+    assert np.allclose(rv.samples, ov.samples, rtol=1e-8, atol=1e-10)
+    assert np.allclose(ra.samples, oa.samples, rtol=1e-8, atol=1e-10)
+    assert np.allclose(ra.mass_history, oa.mass_history, rtol=1e-7)

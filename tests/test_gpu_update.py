@@ -49,6 +49,31 @@ def test_updates_equal_full_evaluation_bitwise(gpu, name, kw, precision):
         assert abs(logL - r["logL"]) <= 1e-10 * abs(r["logL"])
 
 
+def test_c2_update_against_the_oracle(gpu):
+    """At the full 4-state size: logL after single-branch, root and
+    multi-branch updates, and the gradient of the updated partials (pg_grad),
+    against the FP64 oracle at the new lengths (1e-10, A_b rule)."""
+    w = make_workload("C2")
+    B_ = len(w.t)
+    rng = np.random.default_rng(9)
+    root_children = [b for b in range(B_) if w.parent[b] == 2 * w.n_tips - 2]
+    t = w.t.copy()
+    with B.Context(0, B.PG_FP64) as ctx:
+        ctx.set_workload(w)
+        ctx.logL(t)
+        for bs in ([17], root_children, list(rng.choice(B_, 4, replace=False))):
+            new = t[bs] * np.exp(rng.normal(0.0, 0.5, size=len(bs)))
+            logL = ctx.logL_update(bs, new)
+            t[bs] = new
+        grad = ctx.grad()
+    w2 = make_workload("C2")
+    w2.t = t
+    r = O.linear_gradient(*args_of(w2))
+    rep = O.parity_report(logL, grad, r["logL"], r["grad"], r["abs_grad"], 1e-10)
+    print("C2 after updates vs oracle", rep, flush=True)
+    assert rep["ok"], rep
+
+
 def test_update_errors(gpu):
     w = small(n_tips=10, n_patterns=20)
     with B.Context(0, B.PG_FP64) as ctx:

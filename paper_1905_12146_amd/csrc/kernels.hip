@@ -75,6 +75,57 @@ __device__ inline void row_entries(T pmine, T ent[M * M]) {
     row_entries_impl<M, T>(pmine, ent, std::make_integer_sequence<int, M * M>{});
 }
 
+// M = 4: the 16 multiply-adds of a product with a row-distributed 4 x 4
+// matrix, each taking its matrix entry straight from the row broadcast
+// (v_fmac_f64_dpp / v_fmac_f32_dpp with row_newbcast; the compiler emits a
+// separate v_mov_*_dpp per entry instead).  Instruction i adds entry E_i
+// times v[i / 4] to out[i % 4]: the accumulators rotate, so each is
+// rewritten only every 4th instruction, beyond the 2 wait states a DPP
+// instruction needs after a VALU write of any of its operands.  The
+// compiler's hazard checks do not look inside inline assembly, so the block
+// opens with 5 wait states (DPP after a VALU write of its operands or of
+// EXEC) and closes with 2 (for a DPP read of the results right after it).
+#define PG_BC(OP, A, X, E) OP " %[a" #A "], %[p], %[x" #X "] row_newbcast:" #E " row_mask:0xf bank_mask:0xf bound_ctrl:1\n"
+#define PG_FMAC16(OP, E0, E1, E2, E3, E4, E5, E6, E7, E8, E9, E10, E11, E12, E13, E14, E15)                     \
+    "s_nop 4\n" PG_BC(OP, 0, 0, E0) PG_BC(OP, 1, 0, E1) PG_BC(OP, 2, 0, E2) PG_BC(OP, 3, 0, E3)                 \
+        PG_BC(OP, 0, 1, E4) PG_BC(OP, 1, 1, E5) PG_BC(OP, 2, 1, E6) PG_BC(OP, 3, 1, E7) PG_BC(OP, 0, 2, E8)    \
+            PG_BC(OP, 1, 2, E9) PG_BC(OP, 2, 2, E10) PG_BC(OP, 3, 2, E11) PG_BC(OP, 0, 3, E12)                 \
+                PG_BC(OP, 1, 3, E13) PG_BC(OP, 2, 3, E14) PG_BC(OP, 3, 3, E15) "s_nop 1\n"
+#define PG_FMAC16_OPERANDS                                                                                    \
+    : [a0] "+v"(a0), [a1] "+v"(a1), [a2] "+v"(a2), [a3] "+v"(a3)                                              \
+    : [p] "v"(pmine), [x0] "v"(v[0]), [x1] "v"(v[1]), [x2] "v"(v[2]), [x3] "v"(v[3])
+
+// TRANS: out = P^T v (instruction i uses entry i = 4 x + y: out[y] += P[x][y]
+// v[x]); otherwise out = P v (entry 4 (i % 4) + i / 4: out[x] += P[x][y] v[y]).
+// Either way each output sums its four terms in increasing order of the
+// vector index, as the generic loops below do.
+template <typename T, bool TRANS>
+__device__ inline void row_fmac44(T pmine, const T v[4], T out[4]) {
+    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+    if constexpr (sizeof(T) == 8) {
+        if constexpr (TRANS)
+            asm volatile(PG_FMAC16("v_fmac_f64_dpp", 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15)
+                         PG_FMAC16_OPERANDS);
+        else
+            asm volatile(PG_FMAC16("v_fmac_f64_dpp", 0, 4, 8, 12, 1, 5, 9, 13, 2, 6, 10, 14, 3, 7, 11, 15)
+                         PG_FMAC16_OPERANDS);
+    } else {
+        if constexpr (TRANS)
+            asm volatile(PG_FMAC16("v_fmac_f32_dpp", 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15)
+                         PG_FMAC16_OPERANDS);
+        else
+            asm volatile(PG_FMAC16("v_fmac_f32_dpp", 0, 4, 8, 12, 1, 5, 9, 13, 2, 6, 10, 14, 3, 7, 11, 15)
+                         PG_FMAC16_OPERANDS);
+    }
+    out[0] = a0;
+    out[1] = a1;
+    out[2] = a2;
+    out[3] = a3;
+}
+#undef PG_FMAC16_OPERANDS
+#undef PG_FMAC16
+#undef PG_BC
+
 // out = P p with P row-distributed (all lanes of the row must be active).
 // Entry e = x M + y is broadcast and consumed at once; for each x the sum
 // runs over y in increasing order.
@@ -86,6 +137,12 @@ __device__ inline void row_matvec_impl(T pmine, const T p[M], T out[M], std::int
 }
 template <int M, typename T>
 __device__ inline void row_matvec(T pmine, const T p[M], T out[M]) {
+#ifndef PG_NO_FMAC_DPP
+    if constexpr (M == 4) {
+        row_fmac44<T, false>(pmine, p, out);
+        return;
+    }
+#endif
     row_matvec_impl<M, T>(pmine, p, out, std::make_integer_sequence<int, M * M>{});
 }
 
@@ -99,6 +156,12 @@ __device__ inline void row_matvec_t_impl(T pmine, const T u[M], T out[M], std::i
 }
 template <int M, typename T>
 __device__ inline void row_matvec_t(T pmine, const T u[M], T out[M]) {
+#ifndef PG_NO_FMAC_DPP
+    if constexpr (M == 4) {
+        row_fmac44<T, true>(pmine, u, out);
+        return;
+    }
+#endif
     row_matvec_t_impl<M, T>(pmine, u, out, std::make_integer_sequence<int, M * M>{});
 }
 

@@ -516,7 +516,7 @@ __device__ inline void mfma_post_body(const EvalArgs& a, int tile, int4* lds_sch
 // (F holds F_c^T's fragments, issued by the caller).  HESS adds, for
 // Section 2.7, the tile sum of h * (u^T Q^2 m_c) / (u^T m_c) and the
 // per-pattern rho gamma ratio (reduced by hsum_kernel); Q^2's fragments
-// are read from memory (q2op).
+// are staged in LDS like Q's.
 template <bool HESS>
 __device__ inline void mfma_pre_child(const EvalArgs& a, int c, int l, int tile, int s, int lane, const Coef& cf,
                                       const V16& u, const V16& mown, const bf16x8* qop, const bf16x8* q2op,
@@ -566,16 +566,59 @@ __device__ inline void mfma_pre_child(const EvalArgs& a, int c, int l, int tile,
     }
 }
 
-// Tip codes of a node's children, loaded one node ahead (they address the
-// tip tables).
-__device__ inline void codes_issue(const EvalArgs& a, int4 nd, int s, unsigned& ci, unsigned& cj) {
-    if (nd.y < a.n_tips) ci = a.codes[(size_t)nd.y * a.S_pad + s];
-    if (nd.z < a.n_tips) cj = a.codes[(size_t)nd.z * a.S_pad + s];
+// Work items of the pre-order walk: each child of each node of a level is
+// one item (item 2i + w of a level is child w of the level's i-th node), so
+// a level offers twice as many independent items as nodes and a wave holds
+// one child's state at a time.  Items go round-robin over the waves.  The
+// tip codes of the item two ahead are in flight during an item; its own
+// vectors (q of the node, the own and the sibling message or tip-table row)
+// are loaded when the previous item is done, and its F^T fragments load
+// under its Q product.  (Loading the vectors a whole item ahead needs 48
+// more registers per lane and spills at two waves per SIMD.)
+struct PreItem {
+    V16 q, mown, msib;
+};
+
+__device__ inline int item_child(int4 nd, int w) { return w ? nd.z : nd.y; }
+__device__ inline int item_sibling(int4 nd, int w) { return w ? nd.y : nd.z; }
+
+// tip codes of the item's own child (x) and sibling (y)
+__device__ inline uint2 item_codes(const EvalArgs& a, int4 nd, int w, int s) {
+    uint2 cd = {0u, 0u};
+    const int c = item_child(nd, w), b = item_sibling(nd, w);
+    if (c < a.n_tips) cd.x = a.codes[(size_t)c * a.S_pad + s];
+    if (b < a.n_tips) cd.y = a.codes[(size_t)b * a.S_pad + s];
+    return cd;
+}
+
+__device__ inline void item_issue(const EvalArgs& a, int4 nd, int w, uint2 cd, int l, int tile, int lane,
+                                  PreItem& r) {
+    if (nd.x != a.root) {
+        vload(static_cast<const float*>(a.qv) + mvec_off(a, nd.x, tile), lane, r.q);
+    } else {
+        const int g = lane >> 4;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = 16 * mt + 4 * g + i;
+                r.q.v[mt][i] = x < a.M ? (float)a.pi64[x] : 0.f;
+            }
+    }
+    ChildLd co, cb;
+    const int c = item_child(nd, w), b = item_sibling(nd, w);
+    co.code = cd.x;
+    cb.code = cd.y;
+    if (c >= a.n_tips) vload(static_cast<const float*>(a.msg) + mvec_off(a, c, tile), lane, co.v);
+    if (b >= a.n_tips) vload(static_cast<const float*>(a.msg) + mvec_off(a, b, tile), lane, cb.v);
+    child_finish(a, c, l, lane, co, r.mown);
+    child_finish(a, b, l, lane, cb, r.msib);
 }
 
 template <bool HESS>
 __device__ inline void mfma_pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
     __shared__ bf16x8 qop[3 * 8 * 64];
+    __shared__ bf16x8 q2lds[HESS ? 3 * 8 * 64 : 1];
     const int l = tile / a.n_pb, pb = tile % a.n_pb;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int ps = lane & 15, g = lane >> 4;
@@ -588,61 +631,44 @@ __device__ inline void mfma_pre_body(const EvalArgs& a, int tile, int4* lds_sche
         if (l == 0 && wv == 0 && g == 0) logl_block_part(a, pb, ps, r);
     }
     const bf16x8* qsrc = static_cast<const bf16x8*>(a.Qop);
-    const bf16x8* q2op = static_cast<const bf16x8*>(a.Q2op);
+    const bf16x8* q2op = q2lds;
     for (int i = threadIdx.x; i < 3 * 8 * 64; i += blockDim.x) qop[i] = qsrc[i];
+    if constexpr (HESS)
+        for (int i = threadIdx.x; i < 3 * 8 * 64; i += blockDim.x) q2lds[i] = static_cast<const bf16x8*>(a.Q2op)[i];
     stage_schedule(a, lds_sched);
     __syncthreads();
     for (int h = a.n_levels - 1; h >= 0; --h) {
-        const int end = a.level_off[h + 1];
-        int idx = a.level_off[h] + wv;
-        if (idx < end) {
-            int4 nd = sched_at(a, lds_sched, idx);
-            ChildLd ci, cj;
-            codes_issue(a, nd, s, ci.code, cj.code);
+        const int base = a.level_off[h];
+        const int n_it = 2 * (a.level_off[h + 1] - base);
+        int it = wv;
+        if (it < n_it) {
+            int4 nd = sched_at(a, lds_sched, base + it / 2);
+            PreItem cur;
+            item_issue(a, nd, it & 1, item_codes(a, nd, it & 1, s), l, tile, lane, cur);
+            int it1 = it + MW;
+            uint2 cd1 = {0u, 0u};
+            if (it1 < n_it) cd1 = item_codes(a, sched_at(a, lds_sched, base + it1 / 2), it1 & 1, s);
             while (true) {
-                // this node's loads: q, internal children's messages, the
-                // first child's F^T fragments; the next node's tip codes
-                V16 q;
-                if (nd.x != a.root) vload(static_cast<const float*>(a.qv) + mvec_off(a, nd.x, tile), lane, q);
-                if (nd.y >= a.n_tips) vload(static_cast<const float*>(a.msg) + mvec_off(a, nd.y, tile), lane, ci.v);
-                if (nd.z >= a.n_tips) vload(static_cast<const float*>(a.msg) + mvec_off(a, nd.z, tile), lane, cj.v);
-                Frags F;
-                if (nd.y >= a.n_tips) frags_issue(frag_of(a, nd.y, l, 1), lane, F);
-                const int nidx = idx + MW;
-                const bool more = nidx < end;
+                const bool more = it1 < n_it;
                 int4 nn = nd;
-                ChildLd ni, nj;
-                if (more) {
-                    nn = sched_at(a, lds_sched, nidx);
-                    codes_issue(a, nn, s, ni.code, nj.code);
-                }
-                if (nd.x == a.root) {
-#pragma unroll
-                    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int x = 16 * mt + 4 * g + i;
-                            q.v[mt][i] = x < a.M ? (float)a.pi64[x] : 0.f;
-                        }
-                }
-                V16 mi, mj, ui, uj;
-                child_finish(a, nd.y, l, lane, ci, mi);
-                child_finish(a, nd.z, l, lane, cj, mj);
-#pragma unroll
-                for (int mt = 0; mt < 4; ++mt) {
-                    ui.v[mt] = q.v[mt] * mj.v[mt];
-                    uj.v[mt] = q.v[mt] * mi.v[mt];
-                }
-                mfma_pre_child<HESS>(a, nd.y, l, tile, s, lane, cf, ui, mi, qop, q2op, F);
-                // the second child's fragments load under its Q product
+                if (more) nn = sched_at(a, lds_sched, base + it1 / 2);
+                const int it2 = it1 + MW;
+                uint2 cd2 = {0u, 0u};
+                if (it2 < n_it) cd2 = item_codes(a, sched_at(a, lds_sched, base + it2 / 2), it2 & 1, s);
+                const int c = item_child(nd, it & 1);
+                Frags F;
+                if (c >= a.n_tips) frags_issue(frag_of(a, c, l, 1), lane, F);
                 __builtin_amdgcn_sched_barrier(0);
-                if (nd.z >= a.n_tips) frags_issue(frag_of(a, nd.z, l, 1), lane, F);
-                mfma_pre_child<HESS>(a, nd.z, l, tile, s, lane, cf, uj, mj, qop, q2op, F);
+                V16 u;
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) u.v[mt] = cur.q.v[mt] * cur.msib.v[mt];
+                mfma_pre_child<HESS>(a, c, l, tile, s, lane, cf, u, cur.mown, qop, q2op, F);
                 if (!more) break;
                 nd = nn;
-                ci = ni;
-                cj = nj;
-                idx = nidx;
+                item_issue(a, nd, it1 & 1, cd1, l, tile, lane, cur);
+                it = it1;
+                it1 = it2;
+                cd1 = cd2;
             }
         }
         __syncthreads();

@@ -45,6 +45,29 @@ __device__ inline double sum16(double v) {
     return v;
 }
 
+// Any 32-bit DPP control on both halves of a double.
+template <int CTRL>
+__device__ inline double dpp64(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// The row sums of a and of b together (upper: lane 8-15 of its row): the
+// first step leaves a_i + a_{i+8} in lanes 0-7 and b_i + b_{i-8} in lanes
+// 8-15 (each lane sends its partner half the value that half sums), then
+// each half of the row is summed by a mirror and two quad exchanges.  Lane
+// 0 of the row ends with the sum of a, lane 8 with the sum of b, each in a
+// fixed association order.
+__device__ inline double pair_sum16(double a, double b, bool upper) {
+    double v = (upper ? b : a) + row_ror<8>(upper ? a : b);
+    v += dpp64<0x141>(v);  // row_half_mirror
+    v += dpp64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    return v;
+}
+
 __device__ inline unsigned long long tip_mask(const EvalArgs& a, unsigned code, int M) {
     if (code < (unsigned)M) return 1ull << code;
     if (code == 255u) return ~0ull;

@@ -729,14 +729,26 @@ __global__ void __launch_bounds__(LOGL_THREADS) logl_kernel(EvalArgs a) {
 //   tile sum of w_s rho gamma^2 (u^T Q^2 m)/(u^T m)   -> partial2[tile][c]
 //   rho gamma (u^T Q m)/(u^T m) for every pattern     -> r1[c][l][s]
 // so d2 logL/dt_c^2 = sum partial2 - sum_s w_s (sum_l r1)^2.
-// Returns true (and q~_c in qout) when c is internal.
+// u_a^T m_a is the same for both children of a node (sum_x q_x m_i,x m_j,x),
+// so it is formed once per node and its reciprocal (0 when the sum is not
+// positive: no contribution) serves both children's ratios.
+template <int M, typename T>
+__device__ inline double node_rden(const T u[M], const T mown[M]) {
+    T den = T(0);
+#pragma unroll
+    for (int x = 0; x < M; ++x) den = fma(u[x], mown[x], den);
+    return (den > T(0)) ? 1.0 / (double)den : 0.0;
+}
+
+// Child c with its top-of-branch vector u and own message mown; rden from
+// node_rden.  Leaves this lane's gradient term (and, HESS, Hessian term) in
+// term / term2 for the caller's row sums.  Returns true (and q~_c in qout)
+// when c is internal.
 template <int M, typename T, bool HESS, bool NH>
 __device__ inline bool pre_child_core(const EvalArgs& a, int c, int l, int tile, int s, int ps, const Coef& cf,
-                                      const T q[M], const T msib[M], const T mown[M], T pc, T qout[M]) {
-    T u[M];
-#pragma unroll
-    for (int x = 0; x < M; ++x) u[x] = q[x] * msib[x];
-    T den = T(0), num = T(0), num2 = T(0);
+                                      const T u[M], const T mown[M], double rden, T pc, double& term,
+                                      double& term2, T qout[M]) {
+    T num = T(0), num2 = T(0);
     if constexpr (!NH) {
         // the model's Q (kernel arguments for small M)
 #pragma unroll
@@ -745,7 +757,6 @@ __device__ inline bool pre_child_core(const EvalArgs& a, int c, int l, int tile,
 #pragma unroll
             for (int y = 0; y < M; ++y) qm = fma(T(qentry<M>(a, x * M + y)), mown[y], qm);
             num = fma(u[x], qm, num);
-            den = fma(u[x], mown[x], den);
             if constexpr (HESS) {
                 T q2m = T(0);
 #pragma unroll
@@ -763,7 +774,6 @@ __device__ inline bool pre_child_core(const EvalArgs& a, int c, int l, int tile,
 #pragma unroll
             for (int y = 0; y < M; ++y) qm = fma(T(Qc[x * M + y]), mown[y], qm);
             num = fma(u[x], qm, num);
-            den = fma(u[x], mown[x], den);
             if constexpr (HESS) {
                 T q2m = T(0);
 #pragma unroll
@@ -772,15 +782,11 @@ __device__ inline bool pre_child_core(const EvalArgs& a, int c, int l, int tile,
             }
         }
     }
-    const double ratio = (den > T(0)) ? (double)num / (double)den : 0.0;
-    double term = (cf.g > 0.0) ? cf.g * ratio : 0.0;
-    term = sum16(term);
-    if (ps == 0) a.partial[(size_t)tile * a.n_branches + c] = term;
+    const double ratio = (double)num * rden;
+    term = (cf.g > 0.0) ? cf.g * ratio : 0.0;
     if constexpr (HESS) {
-        const double ratio2 = (den > T(0)) ? (double)num2 / (double)den : 0.0;
-        double term2 = (cf.h > 0.0) ? cf.h * ratio2 : 0.0;
-        term2 = sum16(term2);
-        if (ps == 0) a.partial2[(size_t)tile * a.n_branches + c] = term2;
+        const double ratio2 = (double)num2 * rden;
+        term2 = (cf.h > 0.0) ? cf.h * ratio2 : 0.0;
         a.r1[((size_t)c * a.K + l) * a.S_pad + s] = (cf.nw > 0.0) ? cf.nw * ratio : 0.0;
     }
     if (c >= a.n_tips) {
@@ -808,16 +814,45 @@ __device__ inline bool pre_child_core(const EvalArgs& a, int c, int l, int tile,
     return false;
 }
 
-// q~_c goes to LDS (lds_dst) or to memory
-template <int M, typename T, bool HESS, bool NH>
-__device__ inline void pre_child(const EvalArgs& a, int c, int l, int tile, int s, int ps, const Coef& cf,
-                                 const T q[M], const T msib[M], const T mown[M], T pc, T* lds_dst) {
-    T qc[M];
-    if (pre_child_core<M, T, HESS, NH>(a, c, l, tile, s, ps, cf, q, msib, mown, pc, qc)) {
-        T* out = lds_dst ? lds_dst : static_cast<T*>(a.qv) + vec_off(a, c, tile, M) + ps;
-#pragma unroll
-        for (int y = 0; y < M; ++y) out[y * TP] = qc[y];
+// Whether a node's two children reduce their terms together.
+template <bool HESS, bool NH>
+constexpr bool PAIR_TERMS = !HESS && !NH;
+
+// Tile sum of one child's term(s), right after its core step.  Lane 0 of
+// pair_sum16(t, t) depends only on the lower half's association, which is
+// the upper half's too, so every variant forms the same bits for a branch.
+template <bool HESS>
+__device__ inline void store_terms(const EvalArgs& a, int tile, int ps, int c, double t, double h) {
+    const size_t at = (size_t)tile * a.n_branches + c;
+    t = pair_sum16(t, t, ps >= 8);
+    if (ps == 0) a.partial[at] = t;
+    if constexpr (HESS) {
+        h = pair_sum16(h, h, ps >= 8);
+        if (ps == 0) a.partial2[at] = h;
     }
+}
+
+// Tile sums of both children's terms (Eq. GradientWithGamma; HESS: the
+// Section 2.7 term too), reduced together over the row's 16 patterns and
+// stored by lane 0 (first child) and lane 8 (second child) of the row.
+template <bool HESS>
+__device__ inline void store_pair_terms(const EvalArgs& a, int tile, int ps, int4 nd, double t0, double t1,
+                                        double h0, double h1) {
+    const size_t at = (size_t)tile * a.n_branches + (ps < 8 ? nd.y : nd.z);
+    const double t = pair_sum16(t0, t1, ps >= 8);
+    if ((ps & 7) == 0) a.partial[at] = t;
+    if constexpr (HESS) {
+        const double h = pair_sum16(h0, h1, ps >= 8);
+        if ((ps & 7) == 0) a.partial2[at] = h;
+    }
+}
+
+// q~_c goes to LDS (lds_dst) or to memory
+template <int M, typename T>
+__device__ inline void pre_store_q(const EvalArgs& a, int c, int tile, int ps, const T qc[M], T* lds_dst) {
+    T* out = lds_dst ? lds_dst : static_cast<T*>(a.qv) + vec_off(a, c, tile, M) + ps;
+#pragma unroll
+    for (int y = 0; y < M; ++y) out[y * TP] = qc[y];
 }
 
 // Loads of one pre-order node: q of the node, both children's messages and,
@@ -868,8 +903,22 @@ __device__ inline void pre_node(const EvalArgs& a, int4 nd, int l, int tile, int
         if (const int si = rslot(nd.w, 1)) di = top_vec<M, T>(top, si, ps);
         if (const int sj = rslot(nd.w, 2)) dj = top_vec<M, T>(top, sj, ps);
     }
-    pre_child<M, T, HESS, NH>(a, nd.y, l, tile, s, ps, cf, q, mj, mi, pi_, di);
-    pre_child<M, T, HESS, NH>(a, nd.z, l, tile, s, ps, cf, q, mi, mj, pj_, dj);
+    T ui[M], uj[M];
+#pragma unroll
+    for (int x = 0; x < M; ++x) {
+        ui[x] = q[x] * mj[x];
+        uj[x] = q[x] * mi[x];
+    }
+    const double rden = node_rden<M, T>(ui, mi);
+    double t0, t1, h0 = 0.0, h1 = 0.0;
+    T qi[M], qj[M];
+    const bool ini = pre_child_core<M, T, HESS, NH>(a, nd.y, l, tile, s, ps, cf, ui, mi, rden, pi_, t0, h0, qi);
+    if constexpr (!PAIR_TERMS<HESS, NH>) store_terms<HESS>(a, tile, ps, nd.y, t0, h0);
+    const bool inj = pre_child_core<M, T, HESS, NH>(a, nd.z, l, tile, s, ps, cf, uj, mj, rden, pj_, t1, h1, qj);
+    if constexpr (!PAIR_TERMS<HESS, NH>) store_terms<HESS>(a, tile, ps, nd.z, t1, h1);
+    else store_pair_terms<HESS>(a, tile, ps, nd, t0, t1, h0, h1);
+    if (ini) pre_store_q<M, T>(a, nd.y, tile, ps, qi, di);
+    if (inj) pre_store_q<M, T>(a, nd.z, tile, ps, qj, dj);
 }
 
 // Clade part of the pre-order pass (after the top): q of a clade root comes
@@ -915,8 +964,21 @@ __device__ inline void pre_clade_node(const EvalArgs& a, int4 nd, int l, int til
     T m0[M], m1[M], q0[M], q1[M];
     child_msg_all<M, T>(a, nd.y, r.c0, lmask, m0);
     child_msg_all<M, T>(a, nd.z, r.c1, lmask, m1);
-    const bool in0 = pre_child_core<M, T, HESS, NH>(a, nd.y, l, tile, s, ps, cf, q, m1, m0, r.c0.pe, q0);
-    const bool in1 = pre_child_core<M, T, HESS, NH>(a, nd.z, l, tile, s, ps, cf, q, m0, m1, r.c1.pe, q1);
+    T u0[M], u1[M];
+#pragma unroll
+    for (int x = 0; x < M; ++x) {
+        u0[x] = q[x] * m1[x];
+        u1[x] = q[x] * m0[x];
+    }
+    const double rden = node_rden<M, T>(u0, m0);
+    double t0, t1, h0 = 0.0, h1 = 0.0;
+    const bool in0 = pre_child_core<M, T, HESS, NH>(a, nd.y, l, tile, s, ps, cf, u0, m0, rden, r.c0.pe, t0, h0, q0);
+    // the Hessian and per-branch-model variants reduce each child at once
+    // (holding both children's terms spills them at FP32's register budget)
+    if constexpr (!PAIR_TERMS<HESS, NH>) store_terms<HESS>(a, tile, ps, nd.y, t0, h0);
+    const bool in1 = pre_child_core<M, T, HESS, NH>(a, nd.z, l, tile, s, ps, cf, u1, m1, rden, r.c1.pe, t1, h1, q1);
+    if constexpr (!PAIR_TERMS<HESS, NH>) store_terms<HESS>(a, tile, ps, nd.z, t1, h1);
+    else store_pair_terms<HESS>(a, tile, ps, nd, t0, t1, h0, h1);
     // the second child's subtree comes next, then the first child's
     if (in1) {
         if (in0) stack_push<M, T>(stk, sp, q0);

@@ -30,7 +30,7 @@ def check(w, precision, ref=None, branches=None):
     logL, grad = gpu_eval(w, precision)
     r = ref if ref is not None else O.naive_gradient(*args_of(w))
     rep = O.parity_report(logL, grad, r["logL"], r["grad"], r["abs_grad"], TOL[precision], branches=branches)
-    print("dense m=20", precision, w.n_tips, w.n_patterns, w.n_cats, rep, flush=True)
+    print("m", w.n_states, precision, w.n_tips, w.n_patterns, w.n_cats, rep, flush=True)
     assert rep["ok"], rep
     return logL, grad
 
@@ -115,24 +115,40 @@ def _chain_q(m):
     return Q
 
 
-def test_eigen_route_and_its_fallbacks(gpu):
-    """Transition matrices by the eigen-decomposition of Q (a random Q, and
-    Jukes-Cantor with a 19-fold eigenvalue) and by scaling and squaring (a
-    defective Q), each against the oracle (which uses SciPy's expm)."""
+def _cyclic_q(m):
+    """x -> x + 1 (mod m) at rate 1: eigenvalues e^{2 pi i k / m} - 1, so the
+    decomposition has conjugate pairs (the 2 x 2 blocks of the real form)."""
+    Q = -np.eye(m)
+    for x in range(m):
+        Q[x, (x + 1) % m] = 1.0
+    return Q
+
+
+@pytest.mark.parametrize("m", [4, 20])
+def test_eigen_route_and_its_fallbacks(gpu, m):
+    """Transition matrices for a random Q, a cyclic Q with conjugate pairs,
+    Jukes-Cantor with an (m-1)-fold eigenvalue and a defective Q, each
+    against the oracle (which uses SciPy's expm), FP64 and FP32.  The
+    20-state kernels take the eigen-decomposition for the first three and
+    scaling and squaring for the defective one; the 4-state kernels always
+    use scaling and squaring."""
     from tests._fixtures import jc_matrix
     from synth.workloads import simulate_sites
-    for label, Q in (("random", None), ("jukes-cantor", jc_matrix(20)), ("defective", _chain_q(20))):
-        w = small(n_tips=25, n_patterns=40, n_cats=2, n_states=20, seed=71, ambiguous=0.05, mean_t=0.2)
+    cases = (("random", None), ("cyclic", _cyclic_q(m)), ("jukes-cantor", jc_matrix(m)),
+             ("defective", _chain_q(m)))
+    for label, Q in cases:
+        w = small(n_tips=25, n_patterns=40, n_cats=2, n_states=m, seed=71, ambiguous=0.05, mean_t=0.2)
         if Q is not None:
             w.Q = Q
-        if label == "defective":
+        if label in ("defective", "cyclic"):
             # uniform tips can need a jump over most of the chain on one short
             # branch, which the truncated series prices at exactly zero; tips
             # simulated under the chain itself keep every pattern likely
             rng = np.random.Generator(np.random.PCG64(72))
             w.tip_states = simulate_sites(w.parent, w.t, Q, w.pi, w.rates, w.cat_weights, 40, rng)
-        m = 20
         V, Vinv, re, im, kind, cond, resid = B.pg_eigensystem(w.Q) if label != "defective" else (None,) * 7
-        print("dense eigen route", label, cond, resid, flush=True)
+        print("eigen route", m, label, cond, resid, None if kind is None else list(kind), flush=True)
+        if label == "cyclic":
+            assert (np.asarray(kind) != 0).any()
         for precision in (B.PG_FP64, B.PG_FP32):
             check(w, precision)

@@ -209,7 +209,8 @@ def traffic_record(kernel, precision, workload="C2"):
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     src = os.path.join(ROOT, "paper_1905_12146_amd", "csrc",
-                       "kernels_mfma.hip" if precision == "split" else "kernels.hip")
+                       "kernels_mfma.hip" if precision == "split" else
+                       "kernels_dense.hip" if workload == "C5" else "kernels.hip")
     try:
         rec = json.load(open(path))
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()

@@ -140,8 +140,10 @@ int pg_set_model(pg_ctx* ctx, int32_t n_states, const double* Q,
  * pg_set_model.  The gradient and Hessian use each branch's own matrix.
  * Both arrays are copied.  n_models = 0 returns to the homogeneous model.
  * Cleared by pg_set_tree with a different N or pg_set_model with a
- * different m.  Errors: PG_E_STATE (no tree or model), PG_E_INVALID (NULL,
- * index out of range), PG_E_MODEL, PG_E_UNSUPPORTED (PG_SPLIT_BF16). */
+ * different m.  Every precision; the transition matrices of a
+ * non-homogeneous model come from scaling and squaring of each branch's
+ * matrix.  Errors: PG_E_STATE (no tree or model), PG_E_INVALID (NULL, index
+ * out of range), PG_E_MODEL. */
 int pg_set_branch_models(pg_ctx* ctx, int32_t n_models, const double* Q, const int32_t* model_of_branch);
 
 /* Partial re-evaluation: logL after changing the lengths of the n branches
@@ -155,8 +157,8 @@ int pg_set_branch_models(pg_ctx* ctx, int32_t n_models, const double* Q, const i
  * pass; later full evaluations keep the exponents (2 bytes per node,
  * pattern and category).  The result, and the partials it leaves for
  * pg_grad, are bitwise those of a full evaluation at the new lengths.
- * Errors: PG_E_STATE (no such partials), PG_E_INVALID, PG_E_ZERO_LIK,
- * PG_E_UNSUPPORTED (PG_SPLIT_BF16). */
+ * Every precision, split-BF16 included.
+ * Errors: PG_E_STATE (no such partials), PG_E_INVALID, PG_E_ZERO_LIK. */
 int pg_logL_update(pg_ctx* ctx, int32_t n, const int32_t* branches, const double* t_new, double* logL);
 
 /* One evaluation from host memory: t[2N-2] branch lengths in, *logL and,

@@ -192,6 +192,8 @@ float bf16_value(uint16_t h) {
 // operands [mt][ks][part][lane][j] in three BF16 parts, row 16 mt + lane % 16,
 // column 16 (2 ks + j / 4) + 4 (lane / 16) + j % 4 (the kernels' state order
 // of the contraction index).
+void split_qops(pg_ctx* c);
+
 void prepare_split_model(pg_ctx* c) {
     const int m = c->m;
     EigenSystem es;
@@ -219,9 +221,16 @@ void prepare_split_model(pg_ctx* c) {
             c->eKind[j] = es.kind[j];
         }
     }
-    // Q (gradient) and Q^2 (Hessian)
-    auto operands = [&](const std::vector<double>& A, std::vector<uint16_t>& out) {
-        out.assign(MF_QOP_BYTES / 2, 0);
+    split_qops(c);
+}
+
+// Split-BF16 operands (hi, mid, lo A fragments, [mt][ks][part][lane][8]) of
+// Q (gradient) and Q^2 (Hessian): the model's, or with per-branch rate
+// matrices one block per matrix, [model][...].
+void split_qops(pg_ctx* c) {
+    const int m = c->m;
+    const int n = c->bm_n > 0 ? c->bm_n : 1;
+    auto operands = [&](const double* A, uint16_t* out) {
         for (int mt = 0; mt < 4; ++mt)
             for (int ks = 0; ks < 2; ++ks)
                 for (int lane = 0; lane < 64; ++lane)
@@ -238,8 +247,13 @@ void prepare_split_model(pg_ctx* c) {
                             out[((((mt * 2 + ks) * 3 + part) * 64 + lane) * 8) + j] = parts[part];
                     }
     };
-    operands(c->Q, c->Qop);
-    operands(c->Q2, c->Q2op);
+    c->Qop.assign(n * MF_QOP_BYTES / 2, 0);
+    c->Q2op.assign(n * MF_QOP_BYTES / 2, 0);
+    for (int k = 0; k < n; ++k) {
+        const size_t mm = (size_t)k * m * m, o = (size_t)k * MF_QOP_BYTES / 2;
+        operands(c->bm_n > 0 ? &c->bm_Q[mm] : c->Q.data(), &c->Qop[o]);
+        operands(c->bm_n > 0 ? &c->bm_Q2[mm] : c->Q2.data(), &c->Q2op[o]);
+    }
 }
 
 // Dense-state path: an eigen-decomposition of Q (m x m) for the transition
@@ -369,8 +383,8 @@ std::vector<BufSpec> buffer_specs(const Dims& d, bool lean) {
         add("eRe", sizeof(double) * MP);
         add("eIm", sizeof(double) * MP);
         add("eKind", sizeof(int) * MP);
-        add("Qop", MF_QOP_BYTES);
-        add("Q2op", MF_QOP_BYTES);
+        add("Qop", MF_QOP_BYTES * std::max<size_t>(1, d.bm_n));
+        add("Q2op", MF_QOP_BYTES * std::max<size_t>(1, d.bm_n));
     }
     if (dense) {
         add("eV", sizeof(double) * M * M);
@@ -1029,9 +1043,9 @@ int pg_set_model(pg_ctx* c, int32_t m, const double* Q, const double* pi, int32_
         c->rates.assign(rates, rates + K);
         c->catw.assign(catw, catw + K);
         c->qnorm = qnorm;
+        if (old_m != m) c->bm_n = 0;  // branch models have the old state count
         if (c->precision == PG_SPLIT_BF16) prepare_split_model(c);
         else if (dense_states(m)) prepare_dense_model(c);
-        if (old_m != m) c->bm_n = 0;  // branch models have the old state count
         c->model_set = true;
         c->dev_stale = true;
         c->na_stale = true;
@@ -1046,8 +1060,6 @@ int pg_set_branch_models(pg_ctx* c, int32_t n_models, const double* Q, const int
     if (!c->tree_set || !c->model_set) return fail(c, PG_E_STATE, "set the tree and the model first");
     if (n_models < 0) return fail(c, PG_E_INVALID, "n_models < 0");
     if (n_models > 0 && (!Q || !model_of_branch)) return fail(c, PG_E_INVALID, "NULL Q or model_of_branch");
-    if (n_models > 0 && c->precision == PG_SPLIT_BF16)
-        return fail(c, PG_E_UNSUPPORTED, "per-branch rate matrices have no split-BF16 kernel");
     return guarded(c, [&] {
         if (int r0 = settle_host_copies(c)) return r0;
         const int m = c->m, B = 2 * c->n_tips - 2;
@@ -1095,6 +1107,7 @@ int pg_set_branch_models(pg_ctx* c, int32_t n_models, const double* Q, const int
         c->bm_Q2.swap(Q2s);
         c->bm_qnorm.swap(qn);
         c->bm_model.swap(model);
+        if (c->precision == PG_SPLIT_BF16) split_qops(c);
         c->dev_stale = true;
         c->na_stale = true;
         c->have_partials = false;
@@ -1105,8 +1118,6 @@ int pg_set_branch_models(pg_ctx* c, int32_t n_models, const double* Q, const int
 int pg_logL_update(pg_ctx* c, int32_t n, const int32_t* branches, const double* t_new, double* logL) {
     if (!c) return PG_E_INVALID;
     if (n < 0 || (n > 0 && (!branches || !t_new)) || !logL) return fail(c, PG_E_INVALID, "bad arguments");
-    if (c->precision == PG_SPLIT_BF16)
-        return fail(c, PG_E_UNSUPPORTED, "partial re-evaluation has no split-BF16 kernel");
     if (!c->have_partials || c->dev_stale || !c->t_host_valid)
         return fail(c, PG_E_STATE, "no resident partials from a host-pointer evaluation");
     return guarded(c, [&] {

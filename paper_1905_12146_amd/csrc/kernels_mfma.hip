@@ -105,6 +105,9 @@ __device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 // one at a time (lo, mid, hi) so only 16 registers of A are live; the four
 // row blocks interleave so consecutive MFMAs are independent.  Order per
 // k-step: lo*hi, mid*mid, mid*hi, hi*lo, hi*mid, hi*hi (smallest first).
+// FENCE (A in global memory): keep each part's loads next to its MFMAs
+// (hoisted ahead, the loads of all parts would hold 96 registers).
+template <bool FENCE = false>
 __device__ inline void apply3(const bf16x8* __restrict__ A, int lane, const V16& x, V16& acc) {
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
@@ -124,12 +127,14 @@ __device__ inline void apply3(const bf16x8* __restrict__ A, int lane, const V16&
         for (int mt = 0; mt < 4; ++mt) ap[mt] = A[((mt * 2 + ks) * 3 + 2) * 64 + lane];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(ap[mt], xh, acc.v[mt]);
+        if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) ap[mt] = A[((mt * 2 + ks) * 3 + 1) * 64 + lane];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(ap[mt], xm, acc.v[mt]);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) acc.v[mt] = mfma(ap[mt], xh, acc.v[mt]);
+        if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) ap[mt] = A[((mt * 2 + ks) * 3 + 0) * 64 + lane];
 #pragma unroll
@@ -273,14 +278,14 @@ __device__ inline void mfma_pmat_body(const EvalArgs& a, int block) {
     __shared__ double Fs[MP][MP + 1];
     __shared__ double Ws[MP][MP + 1];
     __shared__ double fc[MP], fsn[MP];
-    const int b = block / a.K, l = block % a.K;
+    const int b = a.blist ? a.blist[block / a.K] : block / a.K, l = block % a.K;
     const int tid = threadIdx.x;
     const int x0 = 4 * (tid / 16), y0 = 4 * (tid % 16);
     const int M = a.M;
     const double tb = a.t[b];
     const bool bad = mf_bad_length(tb);
     double acc[4][4];
-    if (!bad && !a.expm_taylor) {
+    if (!bad && !a.expm_taylor && a.n_models == 0) {
         // F = V X with X = (exp(B tau) - I) V^-1: row j of X is
         //   C_j r_j                      (real eigenvalue, C = expm1(re tau))
         //   C r_j + S r_{j+1}, -S r_j + C r_{j+1}   (pair j, j+1; C = e^{a} cos b
@@ -335,7 +340,9 @@ __device__ inline void mfma_pmat_body(const EvalArgs& a, int block) {
         //   G = I + A/2 (I + A/3 (... (I + A/DEG))), F = A G, then s times
         //   F <- 2F + F F.  A is staged in Ws, G (then F) lives in Fs.
         const double h = a.rates[l] * tb;
-        double nrm = a.qnorm * h;
+        // the model's rate matrix, or branch b's own (non-homogeneous model)
+        const double* Qb = a.n_models ? a.Qm + (size_t)a.branch_model[b] * M * M : a.Q64;
+        double nrm = (a.n_models ? a.qnorm_m[a.branch_model[b]] : a.qnorm) * h;
         int sq = 0;
         while (nrm > 0.5 && sq < 1100) {
             nrm *= 0.5;
@@ -344,7 +351,7 @@ __device__ inline void mfma_pmat_body(const EvalArgs& a, int block) {
         const double hs = ldexp(h, -sq);
         for (int e = tid; e < MP * MP; e += blockDim.x) {
             const int x = e / MP, y = e % MP;
-            Ws[x][y] = (x < M && y < M) ? a.Q64[x * M + y] * hs : 0.0;
+            Ws[x][y] = (x < M && y < M) ? Qb[x * M + y] * hs : 0.0;
             Fs[x][y] = (x == y) ? 1.0 : 0.0;
         }
         __syncthreads();
@@ -442,7 +449,19 @@ __device__ inline void mfma_post_node(const EvalArgs& a, int4 nd, int l, int til
     child_finish(a, nd.z, l, lane, cj, mj);
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) p.v[mt] = mi.v[mt] * mj.v[mt];
-    esum += rescale(p);
+    const int e = rescale(p);
+    if (a.expo) {
+        // per-node exponents for partial re-evaluation (lane group 0 owns
+        // them): a pass over some nodes adds the change of each visited
+        // node's exponent
+        if (g == 0) {
+            int16_t* ex = a.expo + ((size_t)(nd.x - a.n_tips) * a.n_tiles + tile) * TP + (lane & 15);
+            esum += a.expo_delta ? e - (int)*ex : e;
+            *ex = (int16_t)e;
+        }
+    } else {
+        esum += e;
+    }
     if (has_msg) {
         V16 acc = p;
         apply3f(F, p, acc);
@@ -504,7 +523,8 @@ __device__ inline void mfma_post_body(const EvalArgs& a, int tile, int4* lds_sch
     if (wv == 0 && g == 0) {
         int tot = 0;
         for (int i = 0; i < MW; ++i) tot += red[i][ps];
-        a.rootE[(size_t)l * a.S_pad + s] = tot;
+        if (a.expo_delta) a.rootE[(size_t)l * a.S_pad + s] += tot;
+        else a.rootE[(size_t)l * a.S_pad + s] = tot;
     }
 }
 
@@ -517,10 +537,10 @@ __device__ inline void mfma_post_body(const EvalArgs& a, int tile, int4* lds_sch
 // Section 2.7, the tile sum of h * (u^T Q^2 m_c) / (u^T m_c) and the
 // per-pattern rho gamma ratio (reduced by hsum_kernel); Q^2's fragments
 // are staged in LDS like Q's.
-template <bool HESS>
+template <bool HESS, bool NH = false>
 __device__ inline void mfma_pre_child(const EvalArgs& a, int c, int l, int tile, int s, int lane, const Coef& cf,
                                       const V16& u, const V16& mown, const bf16x8* qop, const bf16x8* q2op,
-                                      const Frags& F) {
+                                      Frags& F) {
     float den = 0.f;
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
@@ -529,7 +549,7 @@ __device__ inline void mfma_pre_child(const EvalArgs& a, int c, int l, int tile,
     V16 qm;
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) qm.v[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    apply3(qop, lane, mown, qm);
+    apply3<NH>(qop, lane, mown, qm);
     float num = 0.f;
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
@@ -545,7 +565,7 @@ __device__ inline void mfma_pre_child(const EvalArgs& a, int c, int l, int tile,
         V16 q2m;
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) q2m.v[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        apply3(q2op, lane, mown, q2m);
+        apply3<NH>(q2op, lane, mown, q2m);
         float num2 = 0.f;
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
@@ -559,6 +579,12 @@ __device__ inline void mfma_pre_child(const EvalArgs& a, int c, int l, int tile,
         if ((lane >> 4) == 0) a.r1[((size_t)c * a.K + l) * a.S_pad + s] = (cf.nw > 0.0) ? cf.nw * ratio : 0.0;
     }
     if (c >= a.n_tips) {
+        if constexpr (NH || HESS) {
+            // with Q from memory, or the Q^2 product as well, the fragments
+            // load only now (held through the products they would spill)
+            __builtin_amdgcn_sched_barrier(0);
+            frags_issue(frag_of(a, c, l, 1), lane, F);
+        }
         V16 acc = u;
         apply3f(F, u, acc);
         (void)rescale(acc);
@@ -615,10 +641,13 @@ __device__ inline void item_issue(const EvalArgs& a, int4 nd, int w, uint2 cd, i
     child_finish(a, b, l, lane, cb, r.msib);
 }
 
-template <bool HESS>
+// NH: per-branch rate matrices; each child's Q (and Q^2) fragments are
+// read from memory (one block per matrix) instead of the LDS copies.
+template <bool HESS, bool NH>
 __device__ inline void mfma_pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
-    __shared__ bf16x8 qop[3 * 8 * 64];
-    __shared__ bf16x8 q2lds[HESS ? 3 * 8 * 64 : 1];
+    constexpr int QF = 3 * 8 * 64;  // bf16x8 per matrix
+    __shared__ bf16x8 qop[NH ? 1 : QF];
+    __shared__ bf16x8 q2lds[HESS && !NH ? QF : 1];
     const int l = tile / a.n_pb, pb = tile % a.n_pb;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int ps = lane & 15, g = lane >> 4;
@@ -631,10 +660,12 @@ __device__ inline void mfma_pre_body(const EvalArgs& a, int tile, int4* lds_sche
         if (l == 0 && wv == 0 && g == 0) logl_block_part(a, pb, ps, r);
     }
     const bf16x8* qsrc = static_cast<const bf16x8*>(a.Qop);
-    const bf16x8* q2op = q2lds;
-    for (int i = threadIdx.x; i < 3 * 8 * 64; i += blockDim.x) qop[i] = qsrc[i];
-    if constexpr (HESS)
-        for (int i = threadIdx.x; i < 3 * 8 * 64; i += blockDim.x) q2lds[i] = static_cast<const bf16x8*>(a.Q2op)[i];
+    const bf16x8* q2src = static_cast<const bf16x8*>(a.Q2op);
+    if constexpr (!NH) {
+        for (int i = threadIdx.x; i < QF; i += blockDim.x) qop[i] = qsrc[i];
+        if constexpr (HESS)
+            for (int i = threadIdx.x; i < QF; i += blockDim.x) q2lds[i] = q2src[i];
+    }
     stage_schedule(a, lds_sched);
     __syncthreads();
     for (int h = a.n_levels - 1; h >= 0; --h) {
@@ -657,12 +688,21 @@ __device__ inline void mfma_pre_body(const EvalArgs& a, int tile, int4* lds_sche
                 if (it2 < n_it) cd2 = item_codes(a, sched_at(a, lds_sched, base + it2 / 2), it2 & 1, s);
                 const int c = item_child(nd, it & 1);
                 Frags F;
-                if (c >= a.n_tips) frags_issue(frag_of(a, c, l, 1), lane, F);
+                if constexpr (!NH && !HESS)
+                    if (c >= a.n_tips) frags_issue(frag_of(a, c, l, 1), lane, F);
                 __builtin_amdgcn_sched_barrier(0);
                 V16 u;
 #pragma unroll
                 for (int mt = 0; mt < 4; ++mt) u.v[mt] = cur.q.v[mt] * cur.msib.v[mt];
-                mfma_pre_child<HESS>(a, c, l, tile, s, lane, cf, u, cur.mown, qop, q2op, F);
+                const bf16x8* qc = qop;
+                const bf16x8* q2c = q2lds;
+                if constexpr (NH) {
+                    // c is the same in every lane: a scalar base address
+                    const size_t mo = (size_t)__builtin_amdgcn_readfirstlane(a.branch_model[c]) * QF;
+                    qc = qsrc + mo;
+                    q2c = q2src + mo;
+                }
+                mfma_pre_child<HESS, NH>(a, c, l, tile, s, lane, cf, u, cur.mown, qc, q2c, F);
                 if (!more) break;
                 nd = nn;
                 item_issue(a, nd, it1 & 1, cd1, l, tile, lane, cur);
@@ -686,19 +726,19 @@ __global__ void __launch_bounds__(MF_THREADS) mfma_post_kernel(EvalArgs a) {
     mfma_post_body(a, tile, lds_dyn);
 }
 
-template <bool HESS>
+template <bool HESS, bool NH>
 __global__ void __launch_bounds__(MF_THREADS) mfma_pre_kernel(EvalArgs a) {
     extern __shared__ int4 lds_dyn[];
     const int tile = xcd_tile(blockIdx.x, a.n_tiles);
     if (tile >= a.n_tiles) return;
-    mfma_pre_body<HESS>(a, tile, lds_dyn);
+    mfma_pre_body<HESS, NH>(a, tile, lds_dyn);
 }
 
 size_t mfma_post_lds_bytes(const EvalArgs& a) { return sched_lds_bytes(a); }
 size_t mfma_pre_lds_bytes(const EvalArgs& a) { return sched_lds_bytes(a); }
 
 hipError_t launch_mfma_pmat(const EvalArgs& a, hipStream_t st) {
-    mfma_pmat_kernel<<<a.n_branches * a.K, 256, 0, st>>>(a);
+    mfma_pmat_kernel<<<(a.blist ? a.n_blist : a.n_branches) * a.K, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 
@@ -709,8 +749,14 @@ hipError_t launch_mfma_post(const EvalArgs& a, hipStream_t st) {
 
 hipError_t launch_mfma_pre(const EvalArgs& a, hipStream_t st, bool hess) {
     const dim3 grid(N_XCD * xcd_per(a.n_tiles)), block(MF_THREADS);
-    if (hess) mfma_pre_kernel<true><<<grid, block, mfma_pre_lds_bytes(a), st>>>(a);
-    else mfma_pre_kernel<false><<<grid, block, mfma_pre_lds_bytes(a), st>>>(a);
+    const size_t lds = mfma_pre_lds_bytes(a);
+    if (a.n_models > 0) {
+        if (hess) mfma_pre_kernel<true, true><<<grid, block, lds, st>>>(a);
+        else mfma_pre_kernel<false, true><<<grid, block, lds, st>>>(a);
+    } else {
+        if (hess) mfma_pre_kernel<true, false><<<grid, block, lds, st>>>(a);
+        else mfma_pre_kernel<false, false><<<grid, block, lds, st>>>(a);
+    }
     return hipGetLastError();
 }
 

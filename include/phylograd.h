@@ -300,8 +300,9 @@ int pg_eigensystem(int32_t m, const double* Q, double* V, double* Vinv, double* 
  * functions are thread-safe. */
 typedef struct pg_server pg_server;
 
-/* Errors: PG_E_INVALID (NULL, budget <= 0, max_sessions < 1), PG_E_DEVICE,
- * PG_E_UNSUPPORTED (PG_SPLIT_BF16: sessions are batched FP64 / FP32 only). */
+/* precision: PG_FP64, PG_FP32 or PG_SPLIT_BF16 (every session of a server
+ * uses it).  Errors: PG_E_INVALID (NULL, budget <= 0, max_sessions < 1),
+ * PG_E_DEVICE, PG_E_UNSUPPORTED (an unknown precision). */
 int pg_server_create(int device, int precision, int64_t hbm_budget_bytes, int32_t max_sessions,
                      pg_server** out);
 /* Stops the worker (queued calls of admitted sessions finish first) and

@@ -1341,17 +1341,19 @@ hipError_t launch_gsum(const EvalArgs& a, hipStream_t st) {
 
 // ---------------------------------------------------------------- batched launches
 
-int pmat_blocks(const EvalArgs& a) {
-    return a.M <= 8 ? (a.n_branches * a.K + 255) / 256 : a.n_branches * a.K;
+int pmat_blocks(const EvalArgs& a, int precision) {
+    return (a.M <= 8 && precision != PG_SPLIT_BF16) ? (a.n_branches * a.K + 255) / 256 : a.n_branches * a.K;
 }
 int traversal_blocks(const EvalArgs& a) { return a.n_tiles; }
 int gsum_total_blocks(const EvalArgs& a) { return gsum_blocks(a.n_branches) + 1; }
 
 size_t post_lds_bytes(const EvalArgs& a, int precision) {
+    if (precision == PG_SPLIT_BF16) return mfma_post_lds_bytes(a);
     const size_t es = precision == PG_FP32 ? 4 : 8;
     return sched_lds_bytes(a) + clade_stack_bytes(a, post_node_slots(a.M, precision), es);
 }
 size_t pre_lds_bytes(const EvalArgs& a, int precision) {
+    if (precision == PG_SPLIT_BF16) return mfma_pre_lds_bytes(a);
     const size_t es = precision == PG_FP32 ? 4 : 8;
     return sched_lds_bytes(a) +
            std::max(top_lds_bytes(a, es), clade_stack_bytes(a, pre_node_slots(a.M, precision), es));
@@ -1371,6 +1373,12 @@ static hipError_t batch_launch(const BatchLaunch& b, hipStream_t st) {
 
 hipError_t launch_batch(const BatchLaunch& b, hipStream_t st) {
     const int M = b.M, precision = b.precision;
+    if (precision == PG_SPLIT_BF16) {
+        const hipError_t e = launch_mfma_batch(b, st);
+        if (e != hipSuccess) return e;
+        gsum_batch<<<b.gsum_blocks, GS_THREADS, 0, st>>>(b.reqs, b.gsum_map);
+        return hipGetLastError();
+    }
     if (M == 4 && precision == PG_FP64) return batch_launch<4, double>(b, st);
     if (M == 4 && precision == PG_FP32) return batch_launch<4, float>(b, st);
     if (dense_states(M)) {

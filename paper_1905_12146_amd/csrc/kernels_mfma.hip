@@ -734,6 +734,30 @@ __global__ void __launch_bounds__(MF_THREADS) mfma_pre_kernel(EvalArgs a) {
     mfma_pre_body<HESS, NH>(a, tile, lds_dyn);
 }
 
+// Batched entry points for continuous batching: map[blockIdx.x] = {request,
+// block within the request}; a request keeps exactly the blocks, order and
+// results it has alone (the traversal block is the tile itself).
+__global__ void __launch_bounds__(256) mfma_pmat_batch(const EvalArgs* __restrict__ reqs,
+                                                        const int2* __restrict__ map) {
+    const int2 m = map[blockIdx.x];
+    mfma_pmat_body(reqs[m.x], m.y);
+}
+__global__ void __launch_bounds__(MF_THREADS) mfma_post_batch(const EvalArgs* __restrict__ reqs,
+                                                              const int2* __restrict__ map) {
+    extern __shared__ int4 lds_dyn[];
+    const int2 m = map[blockIdx.x];
+    mfma_post_body(reqs[m.x], m.y, lds_dyn);
+}
+__global__ void __launch_bounds__(MF_THREADS) mfma_pre_batch(const EvalArgs* __restrict__ reqs,
+                                                             const int2* __restrict__ map) {
+    extern __shared__ int4 lds_dyn[];
+    const int2 m = map[blockIdx.x];
+    // by value: uniform loads into scalar registers (through the reference
+    // the fields would be held in vector registers, which spill)
+    const EvalArgs a = reqs[m.x];
+    mfma_pre_body<false, false>(a, m.y, lds_dyn);
+}
+
 size_t mfma_post_lds_bytes(const EvalArgs& a) { return sched_lds_bytes(a); }
 size_t mfma_pre_lds_bytes(const EvalArgs& a) { return sched_lds_bytes(a); }
 
@@ -757,6 +781,14 @@ hipError_t launch_mfma_pre(const EvalArgs& a, hipStream_t st, bool hess) {
         if (hess) mfma_pre_kernel<true, false><<<grid, block, lds, st>>>(a);
         else mfma_pre_kernel<false, false><<<grid, block, lds, st>>>(a);
     }
+    return hipGetLastError();
+}
+
+// pmat, post and pre of a serving batch (the caller launches the reduction)
+hipError_t launch_mfma_batch(const BatchLaunch& b, hipStream_t st) {
+    if (b.pmat_blocks > 0) mfma_pmat_batch<<<b.pmat_blocks, 256, 0, st>>>(b.reqs, b.pmat_map);
+    mfma_post_batch<<<b.trav_blocks, MF_THREADS, b.post_lds, st>>>(b.reqs, b.trav_map);
+    mfma_pre_batch<<<b.trav_blocks, MF_THREADS, b.pre_lds, st>>>(b.reqs, b.trav_map);
     return hipGetLastError();
 }
 

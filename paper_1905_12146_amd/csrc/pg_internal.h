@@ -219,13 +219,14 @@ struct BatchLaunch {
     int pmat_blocks, trav_blocks, gsum_blocks;
     size_t post_lds, pre_lds;
 };
-int pmat_blocks(const EvalArgs& a);
+int pmat_blocks(const EvalArgs& a, int precision);
 int traversal_blocks(const EvalArgs& a);
 int gsum_total_blocks(const EvalArgs& a);
 size_t post_lds_bytes(const EvalArgs& a, int precision);
 size_t pre_lds_bytes(const EvalArgs& a, int precision);
 hipError_t launch_batch(const BatchLaunch& b, hipStream_t s);
 hipError_t launch_dense_batch(const BatchLaunch& b, hipStream_t s);  // kernels_dense.hip
+hipError_t launch_mfma_batch(const BatchLaunch& b, hipStream_t s);   // kernels_mfma.hip
 
 // Q = V B V^-1 with B block diagonal (eigen.cpp).  kind[j]: 0 real
 // eigenvalue re[j]; 1 and 2 the two columns (real and imaginary part of the

@@ -290,7 +290,7 @@ int run_group(pg_server* s, std::vector<Item>& items) {
     size_t post_lds = 0, pre_lds = 0;
     for (auto& it : items) {
         t_total += it.args.n_branches;
-        pm += pmat_blocks(it.args);
+        pm += pmat_blocks(it.args, s->precision);
         tr += traversal_blocks(it.args);
         gs += gsum_total_blocks(it.args);
         post_lds = std::max(post_lds, post_lds_bytes(it.args, s->precision));
@@ -329,7 +329,7 @@ int run_group(pg_server* s, std::vector<Item>& items) {
         a.status = reinterpret_cast<int*>(dout + o_status) + q;
         a.grad_out = reinterpret_cast<double*>(dout + o_grad) + toff;
         ha[q] = a;
-        for (int b = 0, nb = pmat_blocks(a); b < nb; ++b) hpm[ipm++] = make_int2(q, b);
+        for (int b = 0, nb = pmat_blocks(a, s->precision); b < nb; ++b) hpm[ipm++] = make_int2(q, b);
         for (int b = 0, nb = traversal_blocks(a); b < nb; ++b) htr[itr++] = make_int2(q, b);
         for (int b = 0, nb = gsum_total_blocks(a); b < nb; ++b) hgs[igs++] = make_int2(q, b);
         toff += a.n_branches;
@@ -426,7 +426,6 @@ extern "C" {
 int pg_server_create(int device, int precision, int64_t hbm_budget, int32_t max_sessions, pg_server** out) {
     if (!out || hbm_budget <= 0 || max_sessions < 1) return PG_E_INVALID;
     *out = nullptr;
-    if (precision == PG_SPLIT_BF16) return PG_E_UNSUPPORTED;  // no batched split-BF16 kernels
     pg_ctx* probe = nullptr;
     int r = pg_create(device, precision, &probe);
     if (r != PG_OK) return r;

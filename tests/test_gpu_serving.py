@@ -72,6 +72,40 @@ def test_served_result_matches_oracle(gpu):
     assert rep["ok"], rep
 
 
+def test_split_sessions_alone_equal_mixed_and_oracle(gpu):
+    """Split-BF16 sessions (61-state codon models and a 4-state one): each
+    request's result is bitwise the same alone, batched with the others and
+    from a single context, and meets the oracle at the path's 1e-5."""
+    from paper_1905_12146_amd.serving import Server
+    ws = [make_workload("C4", seed=300 + i, n_tips=n, n_patterns=s) for i, (n, s) in
+          enumerate([(40, 120), (97, 61), (16, 300), (3, 9)])]
+    ws.append(make_workload("C1", seed=310, n_tips=50, n_patterns=77, n_cats=2))
+    ref = [_single(w, B.PG_SPLIT_BF16) for w in ws]
+    with Server(0, B.PG_SPLIT_BF16, 8 << 30, 16) as srv:
+        alone = []
+        for w in ws:
+            sid = srv.open(w)
+            st, l, g, _ = srv.wait(srv.submit(sid, w.t), len(w.t))
+            assert st == B.PG_OK
+            alone.append((l, g))
+            srv.close(sid)
+        sids = [srv.open(w) for w in ws]
+        tickets = [[srv.submit(sid, w.t * f) for f in (1.0, 0.7)] for sid, w in zip(sids, ws)]
+        mixed = [[srv.wait(tk, len(w.t)) for tk in tks] for tks, w in zip(tickets, ws)]
+        stats = srv.stats()
+        for sid in sids:
+            srv.close(sid)
+    assert stats["max_batch"] >= 2, stats
+    for (lr, gr), (la, ga), mx, w in zip(ref, alone, mixed, ws):
+        assert la == lr and np.array_equal(ga, gr)
+        st, l, g, _ = mx[0]
+        assert st == B.PG_OK and l == la and np.array_equal(g, ga)
+        lin = O.linear_gradient(*args_of(w))
+        rep = O.parity_report(la, ga, lin["logL"], lin["grad"], lin["abs_grad"], 1e-5)
+        print("served split vs oracle", w.n_tips, w.n_patterns, w.n_states, rep, flush=True)
+        assert rep["ok"], rep
+
+
 def test_admission_by_footprint(gpu):
     from paper_1905_12146_amd.serving import Server
     ws = [make_workload("C3", seed=200 + i, n_tips=400, n_patterns=800, tips="uniform") for i in range(6)]

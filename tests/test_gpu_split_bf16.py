@@ -119,9 +119,12 @@ def test_logl_only_then_grad(gpu):
     assert l1 == l2 and np.array_equal(g1, g2)
 
 
-def test_unsupported_calls(gpu):
+def test_server_precisions(gpu):
+    # every precision serves (split-BF16 included); an unknown one is refused
+    h = B.pg_server_create(0, B.PG_SPLIT_BF16, 1 << 30, 4)
+    B.pg_server_destroy(h)
     with pytest.raises(B.PhyloGradError) as e:
-        B.pg_server_create(0, B.PG_SPLIT_BF16, 1 << 30, 4)
+        B.pg_server_create(0, 7, 1 << 30, 4)
     assert e.value.code == B.PG_E_UNSUPPORTED
 
 

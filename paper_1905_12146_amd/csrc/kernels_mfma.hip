@@ -254,24 +254,39 @@ __device__ inline int rescale(V16& v) {
 
 __device__ inline bool mf_bad_length(double t) { return !(t >= 0.0) || isinf(t); }
 
-// 4 x 4 block of C = A B with A and B in LDS (row-major, padded rows).
-__device__ inline void block_product(const double (*A)[MP + 1], const double (*B)[MP + 1], int x0, int y0,
-                                     double acc[4][4]) {
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// C = A B for 64 x 64 FP64 matrices in LDS (row-major, padded rows) on the
+// matrix cores (v_mfma_f64_16x16x4f64), by a workgroup of 4 waves: wave w
+// forms rows 16w..16w+15 (four 16 x 16 tiles), k in steps of 4 (operand
+// lanes: A[i][k] at lane i + 16k, B[k][j] at lane j + 16k).  After a
+// barrier each lane writes out[x][y] = epi(x, y, C[x][y]) for its own
+// elements (item r of tile t at lane j + 16g is row g + 4r, column j), so
+// out may be A or B; ends with a barrier.
+template <typename Epi>
+__device__ inline void lds_product(const double (*A)[MP + 1], const double (*B)[MP + 1], double (*out)[MP + 1],
+                                   Epi epi) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = lane & 15, kk = lane >> 4;
+    d4 acc[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int t = 0; t < 4; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < MP; k0 += 4) {
+        const double av = A[16 * w + i][k0 + kk];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int k = 0; k < MP; ++k) {
-        double av[4], bv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = A[x0 + i][k];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = B[k][y0 + j];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        for (int t = 0; t < 4; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, B[k0 + kk][16 * t + i], acc[t], 0, 0, 0);
     }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int x = 16 * w + kk + 4 * r, y = 16 * t + i;
+            out[x][y] = epi(x, y, acc[t][r]);
+        }
+    __syncthreads();
 }
 
 __device__ inline void mfma_pmat_body(const EvalArgs& a, int block) {
@@ -280,11 +295,10 @@ __device__ inline void mfma_pmat_body(const EvalArgs& a, int block) {
     __shared__ double fc[MP], fsn[MP];
     const int b = a.blist ? a.blist[block / a.K] : block / a.K, l = block % a.K;
     const int tid = threadIdx.x;
-    const int x0 = 4 * (tid / 16), y0 = 4 * (tid % 16);
     const int M = a.M;
     const double tb = a.t[b];
     const bool bad = mf_bad_length(tb);
-    double acc[4][4];
+    auto keep = [](int, int, double c) { return c; };
     if (!bad && !a.expm_taylor && a.n_models == 0) {
         // F = V X with X = (exp(B tau) - I) V^-1: row j of X is
         //   C_j r_j                      (real eigenvalue, C = expm1(re tau))
@@ -334,7 +348,7 @@ __device__ inline void mfma_pmat_body(const EvalArgs& a, int block) {
             Ws[e / MP][e % MP] = wv[i];
         }
         __syncthreads();
-        block_product(Fs, Ws, x0, y0, acc);
+        lds_product(Fs, Ws, Fs, keep);  // F = V X
     } else if (!bad) {
         // F = exp(A) - I, A = Q rate t 2^-s with ||A||_inf <= 1/2:
         //   G = I + A/2 (I + A/3 (... (I + A/DEG))), F = A G, then s times
@@ -356,37 +370,17 @@ __device__ inline void mfma_pmat_body(const EvalArgs& a, int block) {
         }
         __syncthreads();
         for (int k = MF_TAYLOR_DEG; k >= 2; --k) {
-            block_product(Ws, Fs, x0, y0, acc);
-            __syncthreads();
             const double inv = 1.0 / k;
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) Fs[x0 + i][y0 + j] = ((x0 + i == y0 + j) ? 1.0 : 0.0) + acc[i][j] * inv;
-            __syncthreads();
+            lds_product(Ws, Fs, Fs, [inv](int x, int y, double c) { return ((x == y) ? 1.0 : 0.0) + c * inv; });
         }
-        block_product(Ws, Fs, x0, y0, acc);  // F
-        for (int r = 0; r < sq; ++r) {
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) Fs[x0 + i][y0 + j] = acc[i][j];
-            __syncthreads();
-            double f2[4][4];
-            block_product(Fs, Fs, x0, y0, f2);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = 2.0 * acc[i][j] + f2[i][j];
-        }
+        lds_product(Ws, Fs, Fs, keep);  // F
+        for (int r = 0; r < sq; ++r)
+            lds_product(Fs, Fs, Fs, [&](int x, int y, double c) { return 2.0 * Fs[x][y] + c; });
     }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) Fs[x0 + i][y0 + j] = bad ? (double)NAN : acc[i][j];
-    __syncthreads();
+    if (bad) {
+        for (int e = tid; e < MP * MP; e += blockDim.x) Fs[e / MP][e % MP] = (double)NAN;
+        __syncthreads();
+    }
 
     char* slot = static_cast<char*>(a.P) + ((size_t)b * a.K + l) * MF_SLOT_BYTES;
     if (b >= a.n_tips) {

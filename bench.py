@@ -17,7 +17,7 @@ gradient, per-branch reduction) on inputs already resident in HBM.
 Prints one JSON line: `value` is K evaluations over the wall clock around
 them; `eval_time_us` the median / p5 / p95 of per-evaluation HIP-event
 durations; ``roofline`` the dominant kernel's bytes per launch (the
-accounting of `survey_bytes`, with the on-chip lower bound beside it) over
+accounting of `algorithmic_bytes`, with the on-chip lower bound beside it) over
 its mean duration, measured with HIP events recorded by the library on the
 stream the kernel runs on; ``cpu_baseline`` the CPU oracle on bounded
 samples (see `cpu_baseline`).
@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "logL+full-gradient evals/sec, N=1000 4-state; p50/p99 served latency"
 
 
-def survey_bytes(n_tips, n_patterns, n_states, n_cats, elem_bytes):
+def algorithmic_bytes(n_tips, n_patterns, n_states, n_cats, elem_bytes):
     """Bytes the method moves per evaluation (the accounting used for `frac`).
 
     V = K m S elem_bytes is one partial vector, I' = N - 2 internal non-root
@@ -511,7 +511,7 @@ def main():
     ctx.set_timing(False)
     times = ctx.timing()
     avg_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in times.items()}
-    sb = survey_bytes(N, S, m, K, es)
+    sb = algorithmic_bytes(N, S, m, K, es)
     ob = onchip_bytes(N, S, m, K, es)
     dom = max(("post", "pre"), key=lambda k: avg_ms[k])
 

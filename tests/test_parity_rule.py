@@ -74,7 +74,7 @@ def test_non_finite_values_fail(bad):
     assert not O.parity_report(bad, ref["grad"].copy(), ref["logL"], ref["grad"], ref["abs_grad"], 1e-5)["ok"]
 
 
-def test_cancelling_branch_is_judged_against_A_not_against_g():
+def test_cancelling_branch_is_measured_against_A_not_against_g():
     # a branch whose site terms cancel (|g| << A): half the tolerance of A
     # passes although it is far beyond tol relative to g; twice fails
     ref_g = np.array([1e-4, 2.0])
@@ -131,7 +131,7 @@ def test_A_is_the_sum_of_one_site_gradient_magnitudes(route):
 
 
 def test_A_scales_with_the_site_weights():
-    # doubling every weight doubles g and A; the rule's verdict is unchanged
+    # doubling every weight doubles g and A; the rule's outcome is unchanged
     w, _ = _reference(n_tips=5, n_patterns=8, n_cats=1, seed=2)
     a = O.naive_gradient(*args_of(w))
     w2 = args_of(w)[:-1] + (2.0 * w.weights,)

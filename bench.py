@@ -203,6 +203,37 @@ def calibrate_copy():
                       "GB_per_s": 2 * 2 ** 30 / (best * 1e-3) / 1e9}), flush=True)
 
 
+def hbm_reference():
+    """Achievable HBM rates on this GPU beside the 8 TB/s specification:
+    a 1 GiB device-to-device copy (1 GiB read + 1 GiB written) and a 2 GiB
+    write (fill), best of five each, timed with HIP events on the current
+    stream."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def best(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            ev[0].record()
+            fn()
+            ev[1].record()
+            torch.cuda.synchronize()
+            t.append(ev[0].elapsed_time(ev[1]))
+        return min(t) * 1e-3
+
+    x = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    copy = 2 * 2 ** 30 / best(lambda: y.copy_(x)) / 1e9
+    del x, y
+    z = torch.ones(2 ** 29, dtype=torch.float32, device="cuda")
+    write = 2 ** 31 / best(lambda: z.fill_(2.0)) / 1e9
+    del z
+    torch.cuda.empty_cache()
+    return {"copy_GBps": round(copy, 1), "write_GBps": round(write, 1)}
+
+
 def traffic_record(kernel, precision, workload="C2"):
     """HBM bytes per launch measured with rocprofv3 counters for this kernel
     source (profiles/traffic.json), or None if the source has changed."""
@@ -535,6 +566,12 @@ def main():
                                  "frac": round(rate(ob[dom], avg_ms[dom]) / HBM_PEAK_GBS, 4),
                                  "eval_bytes": ob["eval"],
                                  "eval_frac": round(rate(ob["eval"], med_ms) / HBM_PEAK_GBS, 4)}}
+    # what plain copies, reads and writes achieve on this GPU, beside the
+    # dominant kernel's counter-measured bytes over its measured time
+    ref = hbm_reference()
+    if roofline["traffic"]:
+        ref["kernel_traffic_GBps"] = round(rate(roofline["traffic"], avg_ms[dom]), 1)
+    roofline["measured_hbm"] = ref
 
     if prec == B.PG_SPLIT_BF16:
         # executed BF16 matrix-core work of the dominant kernel: 16x16x32

@@ -732,11 +732,14 @@ __global__ void __launch_bounds__(LOGL_THREADS) logl_kernel(EvalArgs a) {
 // u_a^T m_a is the same for both children of a node (sum_x q_x m_i,x m_j,x),
 // so it is formed once per node and its reciprocal (0 when the sum is not
 // positive: no contribution) serves both children's ratios.
+// (FP32 partials: the hardware FP32 reciprocal, within about 1 ulp, far
+// inside that path's accuracy.)
 template <int M, typename T>
 __device__ inline double node_rden(const T u[M], const T mown[M]) {
     T den = T(0);
 #pragma unroll
     for (int x = 0; x < M; ++x) den = fma(u[x], mown[x], den);
+    if constexpr (sizeof(T) == 4) return (den > T(0)) ? (double)__builtin_amdgcn_rcpf(den) : 0.0;
     return (den > T(0)) ? 1.0 / (double)den : 0.0;
 }
 
@@ -818,16 +821,35 @@ __device__ inline bool pre_child_core(const EvalArgs& a, int c, int l, int tile,
 template <bool HESS, bool NH>
 constexpr bool PAIR_TERMS = !HESS && !NH;
 
+// FP32 partials: the row sums in FP32 (single-precision DPP adds; the
+// terms are rounded to FP32 first, far inside that path's accuracy).
+template <int CTRL>
+__device__ inline float dpp32(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+__device__ inline float pair_sum16f(float a, float b, bool upper) {
+    float v = (upper ? b : a) + dpp32<0x128>(upper ? a : b);  // row_ror 8
+    v += dpp32<0x141>(v);                                      // row_half_mirror
+    v += dpp32<0x4E>(v);                                       // quad_perm [2, 3, 0, 1]
+    v += dpp32<0xB1>(v);                                       // quad_perm [1, 0, 3, 2]
+    return v;
+}
+template <typename T>
+__device__ inline double pair_sum_t(double a, double b, bool upper) {
+    if constexpr (sizeof(T) == 4) return (double)pair_sum16f((float)a, (float)b, upper);
+    return pair_sum16(a, b, upper);
+}
+
 // Tile sum of one child's term(s), right after its core step.  Lane 0 of
 // pair_sum16(t, t) depends only on the lower half's association, which is
 // the upper half's too, so every variant forms the same bits for a branch.
-template <bool HESS>
+template <bool HESS, typename T>
 __device__ inline void store_terms(const EvalArgs& a, int tile, int ps, int c, double t, double h) {
     const size_t at = (size_t)tile * a.n_branches + c;
-    t = pair_sum16(t, t, ps >= 8);
+    t = pair_sum_t<T>(t, t, ps >= 8);
     if (ps == 0) a.partial[at] = t;
     if constexpr (HESS) {
-        h = pair_sum16(h, h, ps >= 8);
+        h = pair_sum_t<T>(h, h, ps >= 8);
         if (ps == 0) a.partial2[at] = h;
     }
 }
@@ -835,14 +857,14 @@ __device__ inline void store_terms(const EvalArgs& a, int tile, int ps, int c, d
 // Tile sums of both children's terms (Eq. GradientWithGamma; HESS: the
 // Section 2.7 term too), reduced together over the row's 16 patterns and
 // stored by lane 0 (first child) and lane 8 (second child) of the row.
-template <bool HESS>
+template <bool HESS, typename T>
 __device__ inline void store_pair_terms(const EvalArgs& a, int tile, int ps, int4 nd, double t0, double t1,
                                         double h0, double h1) {
     const size_t at = (size_t)tile * a.n_branches + (ps < 8 ? nd.y : nd.z);
-    const double t = pair_sum16(t0, t1, ps >= 8);
+    const double t = pair_sum_t<T>(t0, t1, ps >= 8);
     if ((ps & 7) == 0) a.partial[at] = t;
     if constexpr (HESS) {
-        const double h = pair_sum16(h0, h1, ps >= 8);
+        const double h = pair_sum_t<T>(h0, h1, ps >= 8);
         if ((ps & 7) == 0) a.partial2[at] = h;
     }
 }
@@ -913,10 +935,10 @@ __device__ inline void pre_node(const EvalArgs& a, int4 nd, int l, int tile, int
     double t0, t1, h0 = 0.0, h1 = 0.0;
     T qi[M], qj[M];
     const bool ini = pre_child_core<M, T, HESS, NH>(a, nd.y, l, tile, s, ps, cf, ui, mi, rden, pi_, t0, h0, qi);
-    if constexpr (!PAIR_TERMS<HESS, NH>) store_terms<HESS>(a, tile, ps, nd.y, t0, h0);
+    if constexpr (!PAIR_TERMS<HESS, NH>) store_terms<HESS, T>(a, tile, ps, nd.y, t0, h0);
     const bool inj = pre_child_core<M, T, HESS, NH>(a, nd.z, l, tile, s, ps, cf, uj, mj, rden, pj_, t1, h1, qj);
-    if constexpr (!PAIR_TERMS<HESS, NH>) store_terms<HESS>(a, tile, ps, nd.z, t1, h1);
-    else store_pair_terms<HESS>(a, tile, ps, nd, t0, t1, h0, h1);
+    if constexpr (!PAIR_TERMS<HESS, NH>) store_terms<HESS, T>(a, tile, ps, nd.z, t1, h1);
+    else store_pair_terms<HESS, T>(a, tile, ps, nd, t0, t1, h0, h1);
     if (ini) pre_store_q<M, T>(a, nd.y, tile, ps, qi, di);
     if (inj) pre_store_q<M, T>(a, nd.z, tile, ps, qj, dj);
 }
@@ -975,10 +997,10 @@ __device__ inline void pre_clade_node(const EvalArgs& a, int4 nd, int l, int til
     const bool in0 = pre_child_core<M, T, HESS, NH>(a, nd.y, l, tile, s, ps, cf, u0, m0, rden, r.c0.pe, t0, h0, q0);
     // the Hessian and per-branch-model variants reduce each child at once
     // (holding both children's terms spills them at FP32's register budget)
-    if constexpr (!PAIR_TERMS<HESS, NH>) store_terms<HESS>(a, tile, ps, nd.y, t0, h0);
+    if constexpr (!PAIR_TERMS<HESS, NH>) store_terms<HESS, T>(a, tile, ps, nd.y, t0, h0);
     const bool in1 = pre_child_core<M, T, HESS, NH>(a, nd.z, l, tile, s, ps, cf, u1, m1, rden, r.c1.pe, t1, h1, q1);
-    if constexpr (!PAIR_TERMS<HESS, NH>) store_terms<HESS>(a, tile, ps, nd.z, t1, h1);
-    else store_pair_terms<HESS>(a, tile, ps, nd, t0, t1, h0, h1);
+    if constexpr (!PAIR_TERMS<HESS, NH>) store_terms<HESS, T>(a, tile, ps, nd.z, t1, h1);
+    else store_pair_terms<HESS, T>(a, tile, ps, nd, t0, t1, h0, h1);
     // the second child's subtree comes next, then the first child's
     if (in1) {
         if (in0) stack_push<M, T>(stk, sp, q0);

@@ -114,14 +114,25 @@ def _linear_chunk(job):
     return r["logL"], r["grad"]
 
 
+def _naive_chunk(job):
+    """One worker of the all-core naive run: a pruning pass per branch of its share."""
+    from threadpoolctl import threadpool_limits
+    import oracle
+    w, branches = job
+    with threadpool_limits(1):
+        r = oracle.naive_gradient(*_oracle_args(w), branches=list(branches))
+    return r["logL"]
+
+
 def cpu_baseline(w, budget_s=10.0):
     """The CPU oracle timed on the host cores, on bounded samples.
 
     Run before the GPU is touched (its all-core leg forks worker processes).
     value: the naive O(N^2) oracle gradient (the parity reference): one
     pruning pass per branch on a sample of branches, scaled to all 2N - 2.
-    others: the paper's O(N) post/pre-order gradient on one core and on all
-    cores (patterns split over worker processes), the pruning logL alone on
+    others: the naive gradient on all cores (a branch sample split over
+    worker processes), the paper's O(N) post/pre-order gradient on one core
+    and on all cores (patterns split over worker processes), the pruning logL alone on
     one core, and central finite differences (two logL per branch, the
     paper's "Numeric" gradient of Section 5.1) on a sample of branches,
     scaled to all branches.  BLAS threads are held to one per process."""
@@ -162,7 +173,20 @@ def cpu_baseline(w, budget_s=10.0):
         t0 = time.perf_counter()
         pool.map(_linear_chunk, [(w, c) for c in chunks])
         t_linN = time.perf_counter() - t0
+        # naive, all cores: n_per branches per worker, each worker's share
+        # costing about a quarter of the budget
+        n_per = int(max(2, 0.25 * budget_s / max(t_logL, 1e-3)))
+        nv_sample = rng.choice(B, size=min(B, n_per * len(chunks)), replace=False)
+        nv_chunks = [c for c in np.array_split(np.sort(nv_sample), len(chunks)) if len(c)]
+        t0 = time.perf_counter()
+        pool.map(_naive_chunk, [(w, c) for c in nv_chunks])
+        t_nvN = time.perf_counter() - t0
+    # every worker also runs one unperturbed pruning pass (the logL) besides its branches
+    per_eval_N = t_nvN / max(len(c) + 1 for c in nv_chunks) * (B / len(nv_chunks) + 1)
     others = [
+        {"kind": "oracle_naive_O(N^2)", "value": 1.0 / per_eval_N, "unit": "evals/s", "cores": len(nv_chunks),
+         "sample": f"naive gradient on {len(nv_sample)} of {B} branches split over {len(nv_chunks)} processes "
+                   f"({t_nvN:.1f} s), scaled to all branches ({per_eval_N:.0f} s)"},
         {"kind": "oracle_linear_O(N)", "value": round(1.0 / t_lin1, 4), "unit": "evals/s", "cores": 1,
          "sample": f"one full evaluation ({t_lin1:.1f} s)"},
         {"kind": "oracle_linear_O(N)", "value": round(1.0 / t_linN, 4), "unit": "evals/s",

@@ -409,6 +409,9 @@ std::vector<BufSpec> buffer_specs(const Dims& d, bool lean) {
     add("rootL", sizeof(double) * K * S_pad);
     add("rootE", sizeof(int) * K * S_pad);
     add("partial", sizeof(double) * n_tiles * B);
+    // clade walks in launches of their own (small M): their exponent sums
+    if (!split && !dense && M * M <= (size_t)TP)
+        add("cl_esum", sizeof(int) * (size_t)(post_node_slots((int)M, d.precision) / CW_WAVES) * n_tiles * TP);
     if (!lean) add("partial2", sizeof(double) * n_tiles * B);
     add("logl_part", sizeof(double) * n_pb);
     add("flag_part", sizeof(int) * n_pb);
@@ -501,6 +504,7 @@ void fill_args(const pg_ctx* c, At&& at, EvalArgs& a) {
         a.cl_pre = pl.one_list ? a.cl_post : a.cl_post + pl.n_cl;
         a.cl_post_off = static_cast<const int*>(at("cl_off"));
         a.cl_pre_off = a.cl_post_off + pl.ns_post + 1;
+        a.cl_esum = static_cast<int*>(at("cl_esum"));
     }
     // stage the schedule in LDS when it fits and leaves each kernel's total
     // within LDS_BLOCK_MAX

@@ -34,6 +34,17 @@ namespace pg {
 
 // ---------------------------------------------------------------- helpers
 
+// Entry i of a schedule or clade list, or of the level offsets, with i the
+// same across the wavefront: read through the constant address space, so it
+// is a scalar load into scalar registers whose wait never holds up the
+// vector loads in flight.
+typedef const __attribute__((address_space(4))) int* cint_ptr;
+__device__ inline int uniform_int(const int* v, int i) { return ((cint_ptr)v)[i]; }
+__device__ inline int4 uniform_entry(const int4* list, int i) {
+    const cint_ptr p = (cint_ptr)(list + i);
+    return make_int4(p[0], p[1], p[2], p[3]);
+}
+
 __device__ inline size_t vec_off(const EvalArgs& a, int node, int tile, int M) {
     return ((size_t)(node - a.n_tips) * a.n_tiles + tile) * (size_t)(M * TP);
 }
@@ -609,27 +620,15 @@ __device__ inline void post_clades(const EvalArgs& a, const int4* lds, int l, in
     }
 }
 
-template <int M, typename T>
-__device__ inline void post_body(const EvalArgs& a, int tile, int4* lds_sched) {
-    constexpr int NS = post_slots<T>(M);
-    const int l = tile / a.n_pb, pb = tile % a.n_pb;
-    const int ps = threadIdx.x % TP, ns = threadIdx.x / TP;
-    const int s = pb * TP + ps;
-    stage_schedule(a, lds_sched, a.n_cl ? a.cl_post : nullptr);
-    int esum = 0;
-    if constexpr (RowMat<M>::value) {
-        // clades first: the top's lowest level reads the clade roots' messages
-        if (a.n_cl) {
-            __shared__ unsigned long long lmask[256];
-            stage_masks(a, lmask);
-            post_clades<M, T>(a, lds_sched, l, tile, s, ps, ns,
-                              clade_stack<M, T>(a, top_buffer<T>(a, lds_sched), ns, ps), lmask, esum);
-            __syncthreads();
-        }
-    }
+// Level walk of the post-order pass over the schedule's levels (the whole
+// tree, or the top above the clades): node slot ns of NS takes every NS-th
+// node of a level; a barrier separates levels.
+template <int M, typename T, int NS>
+__device__ inline void post_levels(const EvalArgs& a, const int4* lds_sched, int l, int tile, int s, int ps, int ns,
+                                   int& esum) {
     for (int h = 0; h < a.n_levels; ++h) {
-        const int end = a.level_off[h + 1];
-        int idx = a.level_off[h] + ns;
+        const int end = uniform_int(a.level_off, h + 1);
+        int idx = uniform_int(a.level_off, h) + ns;
         if (idx < end) {
             // software pipeline: the next node's loads are issued before this
             // node's stores, so they never wait behind them
@@ -664,15 +663,45 @@ __device__ inline void post_body(const EvalArgs& a, int tile, int4* lds_sched) {
         }
         __syncthreads();
     }
+}
+
+// The pattern's summed scale exponent of the tile's category: the NS slots'
+// sums in slot order, plus the parts of a separate clade launch.
+template <int NS>
+__device__ inline void post_root_exponents(const EvalArgs& a, int l, int tile, int s, int ps, int ns, int esum) {
     __shared__ int red[NS][TP];
     red[ns][ps] = esum;
     __syncthreads();
     if (ns == 0) {
         int tot = 0;
         for (int i = 0; i < NS; ++i) tot += red[i][ps];
+        // exponents summed by the separate clade launch, one part per workgroup
+        for (int q = 0; q < a.n_cl_esum; ++q) tot += a.cl_esum[((size_t)q * a.n_tiles + tile) * TP + ps];
         if (a.expo_delta) a.rootE[(size_t)l * a.S_pad + s] += tot;
         else a.rootE[(size_t)l * a.S_pad + s] = tot;
     }
+}
+
+template <int M, typename T>
+__device__ inline void post_body(const EvalArgs& a, int tile, int4* lds_sched) {
+    constexpr int NS = post_slots<T>(M);
+    const int l = tile / a.n_pb, pb = tile % a.n_pb;
+    const int ps = threadIdx.x % TP, ns = threadIdx.x / TP;
+    const int s = pb * TP + ps;
+    stage_schedule(a, lds_sched, a.n_cl ? a.cl_post : nullptr);
+    int esum = 0;
+    if constexpr (RowMat<M>::value) {
+        // clades first: the top's lowest level reads the clade roots' messages
+        if (a.n_cl) {
+            __shared__ unsigned long long lmask[256];
+            stage_masks(a, lmask);
+            post_clades<M, T>(a, lds_sched, l, tile, s, ps, ns,
+                              clade_stack<M, T>(a, top_buffer<T>(a, lds_sched), ns, ps), lmask, esum);
+            __syncthreads();
+        }
+    }
+    post_levels<M, T, NS>(a, lds_sched, l, tile, s, ps, ns, esum);
+    post_root_exponents<NS>(a, l, tile, s, ps, ns, esum);
 }
 
 template <int NT>
@@ -743,14 +772,12 @@ __device__ inline double node_rden(const T u[M], const T mown[M]) {
     return (den > T(0)) ? 1.0 / (double)den : 0.0;
 }
 
-// Child c with its top-of-branch vector u and own message mown; rden from
-// node_rden.  Leaves this lane's gradient term (and, HESS, Hessian term) in
-// term / term2 for the caller's row sums.  Returns true (and q~_c in qout)
-// when c is internal.
+// Gradient term (and, HESS, Hessian term) of child c with its
+// top-of-branch vector u and own message mown; rden from node_rden.  Leaves
+// this lane's terms in term / term2 for the caller's row sums.
 template <int M, typename T, bool HESS, bool NH>
-__device__ inline bool pre_child_core(const EvalArgs& a, int c, int l, int tile, int s, int ps, const Coef& cf,
-                                      const T u[M], const T mown[M], double rden, T pc, double& term,
-                                      double& term2, T qout[M]) {
+__device__ inline void child_terms(const EvalArgs& a, int c, int l, int s, const Coef& cf, const T u[M],
+                                   const T mown[M], double rden, double& term, double& term2) {
     T num = T(0), num2 = T(0);
     if constexpr (!NH) {
         // the model's Q (kernel arguments for small M)
@@ -792,26 +819,42 @@ __device__ inline bool pre_child_core(const EvalArgs& a, int c, int l, int tile,
         term2 = (cf.h > 0.0) ? cf.h * ratio2 : 0.0;
         a.r1[((size_t)c * a.K + l) * a.S_pad + s] = (cf.nw > 0.0) ? cf.nw * ratio : 0.0;
     }
-    if (c >= a.n_tips) {
-        T qc[M];
-        if constexpr (RowMat<M>::value) {
-            row_matvec_t<M, T>(pc, u, qc);
-        } else {
-            const T* Pc = pmat_of<M, T>(a, c, l);
+}
+
+// q~_c = P_c^T u of an internal child c, rescaled by an exact power of two
+// (pc: this lane's entry of the row-distributed P_c for small M).
+template <int M, typename T>
+__device__ inline void child_q(const EvalArgs& a, int c, int l, T pc, const T u[M], T qout[M]) {
+    T qc[M];
+    if constexpr (RowMat<M>::value) {
+        row_matvec_t<M, T>(pc, u, qc);
+    } else {
+        const T* Pc = pmat_of<M, T>(a, c, l);
 #pragma unroll
-            for (int y = 0; y < M; ++y) {
-                T acc = T(0);
+        for (int y = 0; y < M; ++y) {
+            T acc = T(0);
 #pragma unroll
-                for (int x = 0; x < M; ++x) acc = fma(Pc[x * M + y], u[x], acc);
-                qc[y] = acc;
-            }
+            for (int x = 0; x < M; ++x) acc = fma(Pc[x * M + y], u[x], acc);
+            qc[y] = acc;
         }
-        T mx = T(0);
+    }
+    T mx = T(0);
 #pragma unroll
-        for (int y = 0; y < M; ++y) mx = fmax(mx, qc[y]);
-        const int e = (mx > T(0)) ? exp_of(mx) : 0;
+    for (int y = 0; y < M; ++y) mx = fmax(mx, qc[y]);
+    const int e = (mx > T(0)) ? exp_of(mx) : 0;
 #pragma unroll
-        for (int y = 0; y < M; ++y) qout[y] = pow2_scale(qc[y], -e);
+    for (int y = 0; y < M; ++y) qout[y] = pow2_scale(qc[y], -e);
+}
+
+// Both for child c: the terms (child_terms) and, when c is internal, q~_c in
+// qout (returns true).
+template <int M, typename T, bool HESS, bool NH>
+__device__ inline bool pre_child_core(const EvalArgs& a, int c, int l, int tile, int s, int ps, const Coef& cf,
+                                      const T u[M], const T mown[M], double rden, T pc, double& term,
+                                      double& term2, T qout[M]) {
+    child_terms<M, T, HESS, NH>(a, c, l, s, cf, u, mown, rden, term, term2);
+    if (c >= a.n_tips) {
+        child_q<M, T>(a, c, l, pc, u, qout);
         return true;
     }
     return false;
@@ -1074,8 +1117,8 @@ __device__ inline void pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
     // levels below is visible
     if (a.top_level < a.n_levels) {
         int h = a.n_levels - 1;
-        int idx = a.level_off[h] + ns;
-        bool have = idx < a.level_off[h + 1];
+        int idx = uniform_int(a.level_off, h) + ns;
+        bool have = idx < uniform_int(a.level_off, h + 1);
         int4 nd = make_int4(0, 0, 0, 0);
         PreRaw<M, T> cur;
         if (have) {
@@ -1084,8 +1127,9 @@ __device__ inline void pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
         }
         for (; h >= a.top_level; --h) {
             const int h2 = h - 1;
-            const int idx2 = (h2 >= a.top_level) ? a.level_off[h2] + ns : 0;
-            const bool have2 = h2 >= a.top_level && idx2 < a.level_off[h2 + 1];
+            const int hc = max(h2, a.top_level);
+            const int idx2 = (h2 >= a.top_level) ? uniform_int(a.level_off, hc) + ns : 0;
+            const bool have2 = h2 >= a.top_level && idx2 < uniform_int(a.level_off, hc + 1);
             int4 nd2 = make_int4(0, 0, 0, 0);
             PreRaw<M, T> nxt;
             if (have2) {
@@ -1113,8 +1157,8 @@ __device__ inline void pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
     }
     // wide levels: several nodes per slot, software-pipelined
     for (int h = a.top_level - 1; h >= 0; --h) {
-        const int end = a.level_off[h + 1];
-        int idx = a.level_off[h] + ns;
+        const int end = uniform_int(a.level_off, h + 1);
+        int idx = uniform_int(a.level_off, h) + ns;
         if (idx < end) {
             int4 nd = sched_at(a, lds_sched, idx);
             PreRaw<M, T> cur;
@@ -1146,6 +1190,215 @@ __device__ inline void pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
             pre_clades<M, T, HESS, NH>(a, lds_sched, l, tile, s, ps, ns, cf, clade_stack<M, T>(a, top, ns, ps), lmask);
         }
     }
+}
+
+// ---------------------------------------------------------------- clade walks, one list per wave
+//
+// The clade walks as launches of their own (the top levels run in the
+// post-order launch after them and in the pre-order launch before them):
+// here a wavefront walks one clade list for four tiles at once, one tile per
+// 16-lane row, instead of four lists for one tile.  Every entry, and with it
+// whether a child is a tip or internal, is then the same across the
+// wavefront: the entries are read into scalar registers, the tip / internal
+// and stack / register choices are scalar branches that run only the path
+// taken, and node addresses are a scalar base plus a per-lane offset that
+// never changes during the walk.  The per-lane arithmetic is that of the
+// combined kernels above, so both give the same bits.
+//
+// A workgroup holds CW_WAVES lists of one group of four tiles.  Tiles are
+// grouped in pattern-block-major order (t' = pb K + l; with K = 4 a group is
+// the four rate categories of one pattern block); a short last group
+// repeats its last tile, whose rows then compute and store the same values.
+constexpr int CW_ROWS = 64 / TP;  // tiles per group (rows per wavefront)
+
+struct CwLane {
+    int tile, l, pb, s, ps;
+    unsigned vec;  // tile * M * TP + ps: this lane's element of a node's block
+    unsigned pe;   // l * M * M + ps: this lane's entry of a branch's matrices
+};
+
+template <int M>
+__device__ inline CwLane cw_lane(const EvalArgs& a, int group) {
+    const int lane = threadIdx.x % 64, row = lane / TP;
+    CwLane ln;
+    ln.ps = lane % TP;
+    const int tp = min(group * CW_ROWS + row, a.n_tiles - 1);
+    ln.pb = tp / a.K;
+    ln.l = tp % a.K;
+    ln.tile = ln.l * a.n_pb + ln.pb;
+    ln.s = ln.pb * TP + ln.ps;
+    ln.vec = (unsigned)(ln.tile * (M * TP) + ln.ps);
+    ln.pe = (unsigned)(ln.l * (M * M) + ln.ps);
+    return ln;
+}
+
+
+template <int M, typename T>
+__device__ inline const T* node_block(const EvalArgs& a, const void* base, int node) {
+    return static_cast<const T*>(base) + (size_t)(node - a.n_tips) * ((size_t)a.n_tiles * (M * TP));
+}
+template <int M, typename T>
+__device__ inline const T* branch_mats(const EvalArgs& a, int b) {
+    return static_cast<const T*>(a.P) + (size_t)b * a.K * (M * M);
+}
+
+template <int M, typename T>
+__device__ inline void post_clade_load_u(const EvalArgs& a, int4 nd, const CwLane& ln, PostCladeRaw<M, T>& r) {
+    r.code0 = (a.codes + (size_t)(nd.y < a.n_tips ? nd.y : 0) * a.S_pad)[ln.s];
+    r.code1 = (a.codes + (size_t)(nd.z < a.n_tips ? nd.z : 0) * a.S_pad)[ln.s];
+    r.pe0 = branch_mats<M, T>(a, nd.y)[ln.pe];
+    r.pe1 = branch_mats<M, T>(a, nd.z)[ln.pe];
+    r.pk = branch_mats<M, T>(a, nd.x)[ln.pe];
+}
+
+template <int M, typename T>
+__device__ inline void post_clades_u(const EvalArgs& a, int list, const CwLane& ln, T* stk,
+                                     const unsigned long long* lmask, int& esum) {
+    const int beg = uniform_int(a.cl_post_off, list), end = uniform_int(a.cl_post_off, list + 1);
+    if (beg >= end) return;
+    int sp = 0;
+    T acc[M];
+#pragma unroll
+    for (int x = 0; x < M; ++x) acc[x] = T(0);
+    auto entry = [&](int i) { return uniform_entry(a.cl_post, min(i, end - 1)); };
+    int4 nd = entry(beg);
+    int4 nn = entry(beg + 1);
+    PostCladeRaw<M, T> cur;
+    post_clade_load_u<M, T>(a, nd, ln, cur);
+    for (int i = beg;; ++i) {
+        const int4 n2 = entry(i + 2);
+        PostCladeRaw<M, T> nxt;
+        post_clade_load_u<M, T>(a, nn, ln, nxt);
+        T m0[M], m1[M], p[M], mk[M];
+        if (nd.y < a.n_tips) {
+            tip_message<M, T>(cur.code0, cur.pe0, lmask, m0);
+        } else if (nd.z < a.n_tips) {
+#pragma unroll
+            for (int x = 0; x < M; ++x) m0[x] = acc[x];
+        } else {
+            stack_pop<M, T>(stk, sp, m0);
+        }
+        if (nd.z < a.n_tips) {
+            tip_message<M, T>(cur.code1, cur.pe1, lmask, m1);
+        } else {
+#pragma unroll
+            for (int x = 0; x < M; ++x) m1[x] = acc[x];
+        }
+        post_combine<M, T>(a, nd.x, ln.tile, ln.ps, m0, m1, p, esum);
+        row_matvec<M, T>(cur.pk, p, mk);
+        T* out = const_cast<T*>(node_block<M, T>(a, a.msg, nd.x)) + ln.vec;
+#pragma unroll
+        for (int x = 0; x < M; ++x) out[x * TP] = mk[x];
+        if (nd.w & CL_STACK) {
+            stack_push<M, T>(stk, sp, mk);
+        } else {
+#pragma unroll
+            for (int x = 0; x < M; ++x) acc[x] = mk[x];
+        }
+        if (i + 1 >= end) break;
+        nd = nn;
+        nn = n2;
+        cur = nxt;
+    }
+}
+
+template <int M, typename T>
+__device__ inline void child_load_all_u(const EvalArgs& a, int c, const CwLane& ln, ChildAll<M, T>& r) {
+    const bool tip = c < a.n_tips;
+    const T* src = node_block<M, T>(a, a.msg, tip ? a.n_tips : c) + ln.vec;
+#pragma unroll
+    for (int x = 0; x < M; ++x) r.v[x] = src[x * TP];
+    r.code = (a.codes + (size_t)(tip ? c : 0) * a.S_pad)[ln.s];
+    r.pe = branch_mats<M, T>(a, c)[ln.pe];
+}
+
+template <int M, typename T>
+__device__ inline void pre_clade_load_u(const EvalArgs& a, int4 nd, const CwLane& ln, PreCladeRaw<M, T>& r) {
+    const T* src = node_block<M, T>(a, a.qv, (nd.w & CL_ROOT) ? nd.x : a.n_tips) + ln.vec;
+#pragma unroll
+    for (int x = 0; x < M; ++x) r.q[x] = src[x * TP];
+    child_load_all_u<M, T>(a, nd.y, ln, r.c0);
+    child_load_all_u<M, T>(a, nd.z, ln, r.c1);
+}
+
+template <int M, typename T, bool HESS, bool NH>
+__device__ inline void pre_clades_u(const EvalArgs& a, int list, const CwLane& ln, const Coef& cf, T* stk,
+                                    const unsigned long long* lmask) {
+    const int beg = uniform_int(a.cl_pre_off, list), end = uniform_int(a.cl_pre_off, list + 1);
+    const int n = end - beg;
+    if (n <= 0) return;
+    int sp = 0;
+    T acc[M];
+#pragma unroll
+    for (int x = 0; x < M; ++x) acc[x] = T(0);
+    // entry i of the walk is list entry end - 1 - i; entries past the end
+    // reload the last one, so every step issues the same loads
+    auto entry = [&](int i) { return uniform_entry(a.cl_pre, end - 1 - min(i, n - 1)); };
+    int4 nd[CLADE_DEPTH];
+    PreCladeRaw<M, T> raw[CLADE_DEPTH];
+#pragma unroll
+    for (int j = 0; j < CLADE_DEPTH; ++j) {
+        nd[j] = entry(j);
+        pre_clade_load_u<M, T>(a, nd[j], ln, raw[j]);
+    }
+    int4 ne = entry(CLADE_DEPTH);
+    for (int i0 = 0; i0 < n; i0 += CLADE_DEPTH) {
+#pragma unroll
+        for (int j = 0; j < CLADE_DEPTH; ++j) {
+            if (i0 + j < n)
+                pre_clade_node<M, T, HESS, NH>(a, nd[j], ln.l, ln.tile, ln.s, ln.ps, cf, raw[j], lmask, acc, stk, sp);
+            const int4 ne2 = entry(i0 + j + CLADE_DEPTH + 1);
+            nd[j] = ne;
+            pre_clade_load_u<M, T>(a, nd[j], ln, raw[j]);
+            ne = ne2;
+        }
+    }
+}
+
+// LDS stack of this thread's row (wavefront w, row r: slot w * CW_ROWS + r).
+template <int M, typename T>
+__device__ inline T* cw_stack(const EvalArgs& a, T* base) {
+    const int slot = threadIdx.x / TP;
+    return base + (size_t)slot * a.cl_depth * (M * TP) + threadIdx.x % TP;
+}
+
+template <int M, typename T>
+__global__ void __launch_bounds__(CW_WAVES * 64) __attribute__((amdgpu_waves_per_eu(RowMat<M>::value ? 4 : 1)))
+post_clade_kernel(EvalArgs a) {
+    extern __shared__ int4 lds_dyn[];
+    constexpr int NQ = post_slots<T>(M) / CW_WAVES;
+    const int group = blockIdx.x / NQ, q = blockIdx.x % NQ;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const CwLane ln = cw_lane<M>(a, group);
+    __shared__ unsigned long long lmask[256];
+    stage_masks(a, lmask);
+    int esum = 0;
+    post_clades_u<M, T>(a, __builtin_amdgcn_readfirstlane(q * CW_WAVES + wave), ln, cw_stack<M, T>(a, reinterpret_cast<T*>(lds_dyn)), lmask, esum);
+    // this workgroup's part of each pattern's exponent sum, lists in order
+    __shared__ int red[CW_WAVES][64];
+    red[wave][lane] = esum;
+    __syncthreads();
+    if (wave == 0) {
+        int tot = 0;
+#pragma unroll
+        for (int w = 0; w < CW_WAVES; ++w) tot += red[w][lane];
+        a.cl_esum[((size_t)q * a.n_tiles + ln.tile) * TP + ln.ps] = tot;
+    }
+}
+
+template <int M, typename T, bool HESS, bool NH>
+__global__ void __launch_bounds__(CW_WAVES * 64) __attribute__((amdgpu_waves_per_eu(pre_waves<T>(M))))
+pre_clade_kernel(EvalArgs a) {
+    extern __shared__ int4 lds_dyn[];
+    constexpr int NQ = pre_slots<T>(M) / CW_WAVES;
+    const int group = blockIdx.x / NQ, q = blockIdx.x % NQ;
+    const int wave = threadIdx.x / 64;
+    const CwLane ln = cw_lane<M>(a, group);
+    const Coef cf = coef_of(a, ln.l, ln.s, site_likelihood(a, ln.s));
+    __shared__ unsigned long long lmask[256];
+    stage_masks(a, lmask);
+    pre_clades_u<M, T, HESS, NH>(a, __builtin_amdgcn_readfirstlane(q * CW_WAVES + wave), ln, cf,
+                                 cw_stack<M, T>(a, reinterpret_cast<T*>(lds_dyn)), lmask);
 }
 
 // ---------------------------------------------------------------- gradient reduction
@@ -1283,9 +1536,32 @@ hipError_t launch_pmat(const EvalArgs& a, int precision, hipStream_t st) {
     PG_DISPATCH(pmat_launch, a, st);
 }
 
+// Clade walks in their own launches (when the context has the exponent
+// buffer they need): the arguments of the top-level launch drop the clades.
+size_t cw_lds_bytes(const EvalArgs& a, size_t elem) {
+    return elem * (size_t)CW_WAVES * CW_ROWS * a.cl_depth * a.M * TP;
+}
+int cw_groups(const EvalArgs& a) { return (a.n_tiles + CW_ROWS - 1) / CW_ROWS; }
+static bool split_clades(const EvalArgs& a) { return a.n_cl > 0 && a.cl_esum != nullptr; }
+static EvalArgs top_only(const EvalArgs& a, int n_esum) {
+    EvalArgs t = a;
+    t.n_cl = 0;
+    t.cl_depth = 0;
+    t.n_cl_esum = n_esum;
+    return t;
+}
+
 template <int M, typename T>
 static hipError_t post_launch(const EvalArgs& a, hipStream_t st) {
-    post_kernel<M, T><<<a.n_tiles, post_slots<T>(M) * TP, post_lds_bytes(a, sizeof(T) == 4 ? PG_FP32 : PG_FP64), st>>>(a);
+    const int prec = sizeof(T) == 4 ? PG_FP32 : PG_FP64;
+    if (RowMat<M>::value && split_clades(a)) {
+        constexpr int NQ = post_slots<T>(M) / CW_WAVES;
+        post_clade_kernel<M, T><<<cw_groups(a) * NQ, CW_WAVES * 64, cw_lds_bytes(a, sizeof(T)), st>>>(a);
+        const EvalArgs t = top_only(a, NQ);
+        post_kernel<M, T><<<a.n_tiles, post_slots<T>(M) * TP, post_lds_bytes(t, prec), st>>>(t);
+        return hipGetLastError();
+    }
+    post_kernel<M, T><<<a.n_tiles, post_slots<T>(M) * TP, post_lds_bytes(a, prec), st>>>(a);
     return hipGetLastError();
 }
 
@@ -1300,16 +1576,28 @@ hipError_t launch_logl(const EvalArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int M, typename T, bool HESS, bool NH>
+static void pre_launch_variant(const EvalArgs& a, hipStream_t st) {
+    const int prec = sizeof(T) == 4 ? PG_FP32 : PG_FP64;
+    const dim3 block(pre_slots<T>(M) * TP);
+    if (RowMat<M>::value && split_clades(a)) {
+        constexpr int NQ = pre_slots<T>(M) / CW_WAVES;
+        const EvalArgs t = top_only(a, 0);
+        pre_kernel<M, T, HESS, NH><<<a.n_tiles, block, pre_lds_bytes(t, prec), st>>>(t);
+        pre_clade_kernel<M, T, HESS, NH><<<cw_groups(a) * NQ, CW_WAVES * 64, cw_lds_bytes(a, sizeof(T)), st>>>(a);
+        return;
+    }
+    pre_kernel<M, T, HESS, NH><<<a.n_tiles, block, pre_lds_bytes(a, prec), st>>>(a);
+}
+
 template <int M, typename T>
 static hipError_t pre_launch(const EvalArgs& a, hipStream_t st, bool hess) {
-    const size_t lds = pre_lds_bytes(a, sizeof(T) == 4 ? PG_FP32 : PG_FP64);
-    const dim3 grid(a.n_tiles), block(pre_slots<T>(M) * TP);
     if (a.n_models) {
-        if (hess) pre_kernel<M, T, true, true><<<grid, block, lds, st>>>(a);
-        else pre_kernel<M, T, false, true><<<grid, block, lds, st>>>(a);
+        if (hess) pre_launch_variant<M, T, true, true>(a, st);
+        else pre_launch_variant<M, T, false, true>(a, st);
     } else {
-        if (hess) pre_kernel<M, T, true, false><<<grid, block, lds, st>>>(a);
-        else pre_kernel<M, T, false, false><<<grid, block, lds, st>>>(a);
+        if (hess) pre_launch_variant<M, T, true, false>(a, st);
+        else pre_launch_variant<M, T, false, false>(a, st);
     }
     return hipGetLastError();
 }

@@ -18,6 +18,8 @@ namespace pg {
 __host__ __device__ constexpr int node_slots(int M) { return M <= 8 ? 32 : 16; }
 // Branches per block of the gradient reduction.
 constexpr int GS_BRANCHES = 16;
+// Wavefronts (clade lists) per workgroup of the separate clade launches.
+constexpr int CW_WAVES = 4;
 // Node slots of the pre-order kernel (FP64 small M: fewer, heavier slots).
 #ifndef PG_PRE_NS64
 #define PG_PRE_NS64 16
@@ -83,6 +85,10 @@ struct EvalArgs {
     const int* cl_post_off;            // [post slots + 1] slot ranges
     const int4* cl_pre;                // [n_cl]
     const int* cl_pre_off;             // [pre slots + 1]
+    int* cl_esum;                      // [post slots / 4][n_tiles][TP] exponent sums of the
+                                       //   clade launch (NULL: clades walked inside the
+                                       //   traversal kernels)
+    int n_cl_esum;                     // parts of cl_esum the top-level launch adds
     const double* Q64;                 // [M][M]
     const double* Q2_64;               // [M][M] Q*Q
     const double* pi64;                // [M]

@@ -19,6 +19,7 @@
 //
 // Exit status 0 when every check passes; otherwise the first failure is
 // printed and the status is 1.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <random>
@@ -423,6 +424,34 @@ void check_updates(const Tree& t, std::mt19937_64& rng) {
     }
 }
 
+// The separate clade launches (small M): workgroup (group g, part q) of
+// ns / 4 parts per group runs lists 4q..4q+3, one per wavefront; row r of a
+// wavefront takes tile t' = min(4g + r, n_tiles - 1) in pattern-block-major
+// order (t' = pb K + l; stored tile l n_pb + pb).  Every tile is walked for
+// every list, and the per-workgroup exponent parts cl_esum[q][tile][pattern]
+// are all written and inside their buffer.
+void check_clade_launch(int ns, int K, int n_pb) {
+    const int waves = 4, rows = 4, n_tiles = K * n_pb;
+    const int nq = ns / waves, groups = (n_tiles + rows - 1) / rows;
+    CHECK(nq * waves == ns, "lists %d not a multiple of the wavefronts per workgroup", ns);
+    std::vector<int> walked((size_t)ns * n_tiles, 0);
+    std::vector<char> part((size_t)nq * n_tiles, 0);
+    for (int g = 0; g < groups; ++g)
+        for (int q = 0; q < nq; ++q)
+            for (int w = 0; w < waves; ++w)
+                for (int r = 0; r < rows; ++r) {
+                    const int tp = std::min(g * rows + r, n_tiles - 1);
+                    const int pb = tp / K, l = tp % K, tile = l * n_pb + pb;
+                    CHECK(pb >= 0 && pb < n_pb && tile >= 0 && tile < n_tiles, "clade launch tile %d", tile);
+                    const int list = q * waves + w;
+                    CHECK(list < ns, "clade launch list %d of %d", list, ns);
+                    walked[(size_t)list * n_tiles + tile] = 1;
+                    part[(size_t)q * n_tiles + tile] = 1;
+                }
+    for (size_t i = 0; i < walked.size(); ++i) CHECK(walked[i], "list %zu of tile %zu not walked", i / n_tiles, i % n_tiles);
+    for (size_t i = 0; i < part.size(); ++i) CHECK(part[i], "exponent part %zu not written", i);
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -465,6 +494,9 @@ int main(int argc, char** argv) {
         p.ns_pre = c.ns_pre;
         check_plan(t, p);
     }
+    for (int ns : {16, 32})
+        for (int K : {1, 2, 3, 4, 5})
+            for (int n_pb : {1, 2, 3, 125, 313}) check_clade_launch(ns, K, n_pb);
     std::mt19937_64 rng(12146 + t.N);
     check_updates(t, rng);
     std::printf("plan_check N=%d: %d checks passed\n", t.N, g_checks);

@@ -1232,20 +1232,25 @@ __device__ inline CwLane cw_lane(const EvalArgs& a, int group) {
     return ln;
 }
 
-
+// Element offsets in 32 bits (fewer scalar instructions per address): the
+// launcher takes these walks only when every vector buffer holds fewer than
+// 2^31 elements.
 template <int M, typename T>
 __device__ inline const T* node_block(const EvalArgs& a, const void* base, int node) {
-    return static_cast<const T*>(base) + (size_t)(node - a.n_tips) * ((size_t)a.n_tiles * (M * TP));
+    return static_cast<const T*>(base) + (unsigned)((node - a.n_tips) * (a.n_tiles * (M * TP)));
 }
 template <int M, typename T>
 __device__ inline const T* branch_mats(const EvalArgs& a, int b) {
-    return static_cast<const T*>(a.P) + (size_t)b * a.K * (M * M);
+    return static_cast<const T*>(a.P) + (unsigned)(b * a.K * (M * M));
+}
+__device__ inline const uint8_t* code_row(const EvalArgs& a, int tip) {
+    return a.codes + (unsigned)(tip * a.S_pad);
 }
 
 template <int M, typename T>
 __device__ inline void post_clade_load_u(const EvalArgs& a, int4 nd, const CwLane& ln, PostCladeRaw<M, T>& r) {
-    r.code0 = (a.codes + (size_t)(nd.y < a.n_tips ? nd.y : 0) * a.S_pad)[ln.s];
-    r.code1 = (a.codes + (size_t)(nd.z < a.n_tips ? nd.z : 0) * a.S_pad)[ln.s];
+    r.code0 = code_row(a, nd.y < a.n_tips ? nd.y : 0)[ln.s];
+    r.code1 = code_row(a, nd.z < a.n_tips ? nd.z : 0)[ln.s];
     r.pe0 = branch_mats<M, T>(a, nd.y)[ln.pe];
     r.pe1 = branch_mats<M, T>(a, nd.z)[ln.pe];
     r.pk = branch_mats<M, T>(a, nd.x)[ln.pe];
@@ -1308,7 +1313,7 @@ __device__ inline void child_load_all_u(const EvalArgs& a, int c, const CwLane& 
     const T* src = node_block<M, T>(a, a.msg, tip ? a.n_tips : c) + ln.vec;
 #pragma unroll
     for (int x = 0; x < M; ++x) r.v[x] = src[x * TP];
-    r.code = (a.codes + (size_t)(tip ? c : 0) * a.S_pad)[ln.s];
+    r.code = code_row(a, tip ? c : 0)[ln.s];
     r.pe = branch_mats<M, T>(a, c)[ln.pe];
 }
 
@@ -1542,7 +1547,12 @@ size_t cw_lds_bytes(const EvalArgs& a, size_t elem) {
     return elem * (size_t)CW_WAVES * CW_ROWS * a.cl_depth * a.M * TP;
 }
 int cw_groups(const EvalArgs& a) { return (a.n_tiles + CW_ROWS - 1) / CW_ROWS; }
-static bool split_clades(const EvalArgs& a) { return a.n_cl > 0 && a.cl_esum != nullptr; }
+static bool split_clades(const EvalArgs& a) {
+    // the separate walks form element offsets in 32 bits
+    const size_t vec_elems = (size_t)a.n_nodes * a.n_tiles * a.M * TP;
+    return a.n_cl > 0 && a.cl_esum != nullptr && vec_elems < (size_t(1) << 31) &&
+           (size_t)a.n_nodes * a.S_pad < (size_t(1) << 31);
+}
 static EvalArgs top_only(const EvalArgs& a, int n_esum) {
     EvalArgs t = a;
     t.n_cl = 0;

@@ -44,6 +44,17 @@ def check(w, precision, label):
 
 
 @pytest.mark.parametrize("precision", [B.PG_FP64, B.PG_FP32])
+@pytest.mark.parametrize("n_cats,n_patterns", [(3, 53), (5, 17), (1, 33), (2, 200)])
+def test_clade_launch_tile_groups(gpu, precision, n_cats, n_patterns):
+    # the separate clade launches give a wavefront four tiles in
+    # pattern-block-major order: groups that mix categories and pattern
+    # blocks, and a short last group (53 patterns x 3 categories: 12 tiles;
+    # 17 x 5: 10 tiles; 33 x 1: 3 tiles; 200 x 2: 26 tiles)
+    w = make_workload("C2", n_tips=120, n_patterns=n_patterns, n_cats=n_cats)
+    check(w, precision, f"N=120 S={n_patterns} K={n_cats} precision={precision}")
+
+
+@pytest.mark.parametrize("precision", [B.PG_FP64, B.PG_FP32])
 def test_schedule_in_memory(gpu, precision):
     # 3000 tips: 2999 schedule entries exceed the LDS budget for staging
     w = make_workload("C2", n_tips=3000, n_patterns=37)

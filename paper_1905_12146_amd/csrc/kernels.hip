@@ -1368,17 +1368,16 @@ __device__ inline T* cw_stack(const EvalArgs& a, T* base) {
 }
 
 template <int M, typename T>
-__global__ void __launch_bounds__(CW_WAVES * 64) __attribute__((amdgpu_waves_per_eu(RowMat<M>::value ? 4 : 1)))
-post_clade_kernel(EvalArgs a) {
-    extern __shared__ int4 lds_dyn[];
+__device__ inline void post_clade_body(const EvalArgs& a, int block, int4* lds_dyn) {
     constexpr int NQ = post_slots<T>(M) / CW_WAVES;
-    const int group = blockIdx.x / NQ, q = blockIdx.x % NQ;
+    const int group = block / NQ, q = block % NQ;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const CwLane ln = cw_lane<M>(a, group);
     __shared__ unsigned long long lmask[256];
     stage_masks(a, lmask);
     int esum = 0;
-    post_clades_u<M, T>(a, __builtin_amdgcn_readfirstlane(q * CW_WAVES + wave), ln, cw_stack<M, T>(a, reinterpret_cast<T*>(lds_dyn)), lmask, esum);
+    post_clades_u<M, T>(a, __builtin_amdgcn_readfirstlane(q * CW_WAVES + wave), ln,
+                        cw_stack<M, T>(a, reinterpret_cast<T*>(lds_dyn)), lmask, esum);
     // this workgroup's part of each pattern's exponent sum, lists in order
     __shared__ int red[CW_WAVES][64];
     red[wave][lane] = esum;
@@ -1392,11 +1391,9 @@ post_clade_kernel(EvalArgs a) {
 }
 
 template <int M, typename T, bool HESS, bool NH>
-__global__ void __launch_bounds__(CW_WAVES * 64) __attribute__((amdgpu_waves_per_eu(pre_waves<T>(M))))
-pre_clade_kernel(EvalArgs a) {
-    extern __shared__ int4 lds_dyn[];
+__device__ inline void pre_clade_body(const EvalArgs& a, int block, int4* lds_dyn) {
     constexpr int NQ = pre_slots<T>(M) / CW_WAVES;
-    const int group = blockIdx.x / NQ, q = blockIdx.x % NQ;
+    const int group = block / NQ, q = block % NQ;
     const int wave = threadIdx.x / 64;
     const CwLane ln = cw_lane<M>(a, group);
     const Coef cf = coef_of(a, ln.l, ln.s, site_likelihood(a, ln.s));
@@ -1404,6 +1401,40 @@ pre_clade_kernel(EvalArgs a) {
     stage_masks(a, lmask);
     pre_clades_u<M, T, HESS, NH>(a, __builtin_amdgcn_readfirstlane(q * CW_WAVES + wave), ln, cf,
                                  cw_stack<M, T>(a, reinterpret_cast<T*>(lds_dyn)), lmask);
+}
+
+// Single evaluation (block = blockIdx.x) and batched entries (map[blockIdx.x]
+// = {request, block}) of the clade launches; one block map serves both
+// passes, whose list counts agree for small M.
+static_assert(post_slots<double>(4) == pre_slots<double>(4) && post_slots<float>(4) == pre_slots<float>(4),
+              "the post- and pre-order clade launches share their block map");
+
+template <int M, typename T>
+__global__ void __launch_bounds__(CW_WAVES * 64) __attribute__((amdgpu_waves_per_eu(RowMat<M>::value ? 4 : 1)))
+post_clade_kernel(EvalArgs a) {
+    extern __shared__ int4 lds_dyn[];
+    post_clade_body<M, T>(a, blockIdx.x, lds_dyn);
+}
+template <int M, typename T>
+__global__ void __launch_bounds__(CW_WAVES * 64) __attribute__((amdgpu_waves_per_eu(RowMat<M>::value ? 4 : 1)))
+post_clade_batch(const EvalArgs* __restrict__ reqs, const int2* __restrict__ map) {
+    extern __shared__ int4 lds_dyn[];
+    const int2 m = map[blockIdx.x];
+    post_clade_body<M, T>(reqs[m.x], m.y, lds_dyn);
+}
+
+template <int M, typename T, bool HESS, bool NH>
+__global__ void __launch_bounds__(CW_WAVES * 64) __attribute__((amdgpu_waves_per_eu(pre_waves<T>(M))))
+pre_clade_kernel(EvalArgs a) {
+    extern __shared__ int4 lds_dyn[];
+    pre_clade_body<M, T, HESS, NH>(a, blockIdx.x, lds_dyn);
+}
+template <int M, typename T>
+__global__ void __launch_bounds__(CW_WAVES * 64) __attribute__((amdgpu_waves_per_eu(pre_waves<T>(M))))
+pre_clade_batch(const EvalArgs* __restrict__ reqs, const int2* __restrict__ map) {
+    extern __shared__ int4 lds_dyn[];
+    const int2 m = map[blockIdx.x];
+    pre_clade_body<M, T, false, false>(reqs[m.x], m.y, lds_dyn);
 }
 
 // ---------------------------------------------------------------- gradient reduction
@@ -1560,6 +1591,21 @@ static EvalArgs top_only(const EvalArgs& a, int n_esum) {
     t.n_cl_esum = n_esum;
     return t;
 }
+static bool small_clades(const EvalArgs& a, int precision) {
+    return (precision == PG_FP64 || precision == PG_FP32) && a.M * a.M <= TP && split_clades(a);
+}
+static int clade_parts(int precision) {
+    return (precision == PG_FP32 ? post_slots<float>(4) : post_slots<double>(4)) / CW_WAVES;
+}
+int clade_blocks(const EvalArgs& a, int precision) {
+    return small_clades(a, precision) ? cw_groups(a) * clade_parts(precision) : 0;
+}
+EvalArgs clade_top_args(const EvalArgs& a, int precision) {
+    return small_clades(a, precision) ? top_only(a, clade_parts(precision)) : a;
+}
+size_t clade_lds_bytes(const EvalArgs& a, int precision) {
+    return small_clades(a, precision) ? cw_lds_bytes(a, precision == PG_FP32 ? 4 : 8) : 0;
+}
 
 template <int M, typename T>
 static hipError_t post_launch(const EvalArgs& a, hipStream_t st) {
@@ -1685,8 +1731,15 @@ static hipError_t batch_launch(const BatchLaunch& b, hipStream_t st) {
         if constexpr (M <= 8) pmat_reg_batch<M, T><<<b.pmat_blocks, 256, 0, st>>>(b.reqs, b.pmat_map);
         else pmat_lds_batch<M, T><<<b.pmat_blocks, 256, 0, st>>>(b.reqs, b.pmat_map);
     }
-    post_batch<M, T><<<b.trav_blocks, post_slots<T>(M) * TP, b.post_lds, st>>>(b.reqs, b.trav_map);
-    pre_batch<M, T><<<b.trav_blocks, pre_slots<T>(M) * TP, b.pre_lds, st>>>(b.reqs, b.trav_map);
+    // requests with clades: their clade walks in the clade launches, their
+    // top levels in the traversal launches (reqs_top)
+    const EvalArgs* top = b.reqs_top ? b.reqs_top : b.reqs;
+    if (b.clade_blocks > 0)
+        post_clade_batch<M, T><<<b.clade_blocks, CW_WAVES * 64, b.clade_lds, st>>>(b.reqs, b.clade_map);
+    post_batch<M, T><<<b.trav_blocks, post_slots<T>(M) * TP, b.post_lds, st>>>(top, b.trav_map);
+    pre_batch<M, T><<<b.trav_blocks, pre_slots<T>(M) * TP, b.pre_lds, st>>>(top, b.trav_map);
+    if (b.clade_blocks > 0)
+        pre_clade_batch<M, T><<<b.clade_blocks, CW_WAVES * 64, b.clade_lds, st>>>(b.reqs, b.clade_map);
     gsum_batch<<<b.gsum_blocks, GS_THREADS, 0, st>>>(b.reqs, b.gsum_map);
     return hipGetLastError();
 }

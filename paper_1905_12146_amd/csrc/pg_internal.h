@@ -219,12 +219,19 @@ size_t mfma_pre_lds_bytes(const EvalArgs& a);
 struct BatchLaunch {
     int M, precision;
     const EvalArgs* reqs;
+    const EvalArgs* reqs_top;  // the traversal launches' arguments (clade_top_args), or NULL: reqs
     const int2* pmat_map;
     const int2* trav_map;
     const int2* gsum_map;
-    int pmat_blocks, trav_blocks, gsum_blocks;
-    size_t post_lds, pre_lds;
+    const int2* clade_map;     // {request, block} of the clade launches
+    int pmat_blocks, trav_blocks, gsum_blocks, clade_blocks;
+    size_t post_lds, pre_lds, clade_lds;
 };
+// Separate clade launches of small-M requests: their blocks (0: none), the
+// arguments of their top-level (traversal) launches, their dynamic LDS.
+int clade_blocks(const EvalArgs& a, int precision);
+EvalArgs clade_top_args(const EvalArgs& a, int precision);
+size_t clade_lds_bytes(const EvalArgs& a, int precision);
 int pmat_blocks(const EvalArgs& a, int precision);
 int traversal_blocks(const EvalArgs& a);
 int gsum_total_blocks(const EvalArgs& a);

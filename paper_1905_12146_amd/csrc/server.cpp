@@ -284,24 +284,30 @@ struct Item {
 // Run one batch of calls with the same state count; mu is not held.
 int run_group(pg_server* s, std::vector<Item>& items) {
     const int n = (int)items.size();
-    // input layout: [t of every call][EvalArgs x n][pmat map][trav map][gsum map]
+    // input layout: [t of every call][EvalArgs x n][top-level EvalArgs x n]
+    // [pmat map][trav map][gsum map][clade map]
     size_t t_total = 0;
-    int pm = 0, tr = 0, gs = 0;
-    size_t post_lds = 0, pre_lds = 0;
+    int pm = 0, tr = 0, gs = 0, cl = 0;
+    size_t post_lds = 0, pre_lds = 0, clade_lds = 0;
     for (auto& it : items) {
+        const EvalArgs top = clade_top_args(it.args, s->precision);
         t_total += it.args.n_branches;
         pm += pmat_blocks(it.args, s->precision);
         tr += traversal_blocks(it.args);
         gs += gsum_total_blocks(it.args);
-        post_lds = std::max(post_lds, post_lds_bytes(it.args, s->precision));
-        pre_lds = std::max(pre_lds, pre_lds_bytes(it.args, s->precision));
+        cl += clade_blocks(it.args, s->precision);
+        post_lds = std::max(post_lds, post_lds_bytes(top, s->precision));
+        pre_lds = std::max(pre_lds, pre_lds_bytes(top, s->precision));
+        clade_lds = std::max(clade_lds, clade_lds_bytes(it.args, s->precision));
     }
     const size_t off_t = 0;
     const size_t off_args = align16(off_t + sizeof(double) * t_total);
-    const size_t off_pm = align16(off_args + sizeof(EvalArgs) * n);
+    const size_t off_top = align16(off_args + sizeof(EvalArgs) * n);
+    const size_t off_pm = align16(off_top + sizeof(EvalArgs) * n);
     const size_t off_tr = align16(off_pm + sizeof(int2) * pm);
     const size_t off_gs = align16(off_tr + sizeof(int2) * tr);
-    const size_t in_bytes = align16(off_gs + sizeof(int2) * gs);
+    const size_t off_cl = align16(off_gs + sizeof(int2) * gs);
+    const size_t in_bytes = align16(off_cl + sizeof(int2) * cl);
     // output layout: [logL x n][status x n][grad of every call]
     const size_t o_logl = 0;
     const size_t o_status = align16(sizeof(double) * n);
@@ -315,11 +321,13 @@ int run_group(pg_server* s, std::vector<Item>& items) {
     char* dout = static_cast<char*>(s->d_out);
     double* ht = reinterpret_cast<double*>(hi + off_t);
     EvalArgs* ha = reinterpret_cast<EvalArgs*>(hi + off_args);
+    EvalArgs* htop = reinterpret_cast<EvalArgs*>(hi + off_top);
     int2* hpm = reinterpret_cast<int2*>(hi + off_pm);
     int2* htr = reinterpret_cast<int2*>(hi + off_tr);
     int2* hgs = reinterpret_cast<int2*>(hi + off_gs);
+    int2* hcl = reinterpret_cast<int2*>(hi + off_cl);
     size_t toff = 0;
-    int ipm = 0, itr = 0, igs = 0;
+    int ipm = 0, itr = 0, igs = 0, icl = 0;
     for (int q = 0; q < n; ++q) {
         Item& it = items[q];
         EvalArgs a = it.args;
@@ -329,9 +337,11 @@ int run_group(pg_server* s, std::vector<Item>& items) {
         a.status = reinterpret_cast<int*>(dout + o_status) + q;
         a.grad_out = reinterpret_cast<double*>(dout + o_grad) + toff;
         ha[q] = a;
+        htop[q] = clade_top_args(a, s->precision);
         for (int b = 0, nb = pmat_blocks(a, s->precision); b < nb; ++b) hpm[ipm++] = make_int2(q, b);
         for (int b = 0, nb = traversal_blocks(a); b < nb; ++b) htr[itr++] = make_int2(q, b);
         for (int b = 0, nb = gsum_total_blocks(a); b < nb; ++b) hgs[igs++] = make_int2(q, b);
+        for (int b = 0, nb = clade_blocks(a, s->precision); b < nb; ++b) hcl[icl++] = make_int2(q, b);
         toff += a.n_branches;
     }
     hipError_t e;
@@ -341,14 +351,18 @@ int run_group(pg_server* s, std::vector<Item>& items) {
     bl.M = items[0].args.M;
     bl.precision = s->precision;
     bl.reqs = reinterpret_cast<const EvalArgs*>(di + off_args);
+    bl.reqs_top = reinterpret_cast<const EvalArgs*>(di + off_top);
     bl.pmat_map = reinterpret_cast<const int2*>(di + off_pm);
     bl.trav_map = reinterpret_cast<const int2*>(di + off_tr);
     bl.gsum_map = reinterpret_cast<const int2*>(di + off_gs);
+    bl.clade_map = reinterpret_cast<const int2*>(di + off_cl);
     bl.pmat_blocks = pm;
     bl.trav_blocks = tr;
     bl.gsum_blocks = gs;
+    bl.clade_blocks = cl;
     bl.post_lds = post_lds;
     bl.pre_lds = pre_lds;
+    bl.clade_lds = clade_lds;
     if ((e = launch_batch(bl, s->stream)) != hipSuccess) return PG_E_DEVICE;
     if ((e = hipMemcpyAsync(s->h_out, s->d_out, out_bytes, hipMemcpyDeviceToHost, s->stream)) != hipSuccess)
         return PG_E_DEVICE;

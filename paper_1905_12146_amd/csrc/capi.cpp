@@ -337,7 +337,10 @@ void ensure_plan(pg_ctx* c) {
     PlanParams p;
     p.n_states = c->m;
     p.elem_bytes = (int)elem_size(c->precision);
-    p.clades = !split && c->m * c->m <= TP;
+    // clade walks (small M) form 32-bit element offsets: every vector
+    // buffer must hold fewer than 2^31 elements, else the level walk serves
+    const size_t nodes = 2 * (size_t)c->n_tips - 1, lim = size_t(1) << 31;
+    p.clades = !split && c->m * c->m <= TP && nodes * c->K * c->S_pad * c->m < lim && nodes * c->S_pad < lim;
     p.top_region = !split && !dense_states(c->m);
     p.ns_post = split ? node_slots(c->m) : post_node_slots(c->m, c->precision);
     p.ns_pre = split ? p.ns_post : pre_node_slots(c->m, c->precision);
@@ -508,7 +511,7 @@ void fill_args(const pg_ctx* c, At&& at, EvalArgs& a) {
     }
     // stage the schedule in LDS when it fits and leaves each kernel's total
     // within LDS_BLOCK_MAX
-    a.sched_lds = (sizeof(int4) * (size_t)(pl.n_top + pl.n_cl) <= (size_t)SCHED_LDS_MAX) ? 1 : 0;
+    a.sched_lds = (sizeof(int4) * (size_t)pl.n_top <= (size_t)SCHED_LDS_MAX) ? 1 : 0;
     if (!split && (post_lds_bytes(a, c->precision) > (size_t)LDS_BLOCK_MAX ||
                    pre_lds_bytes(a, c->precision) > (size_t)LDS_BLOCK_MAX))
         a.sched_lds = 0;

@@ -90,21 +90,10 @@ __device__ inline int4 sched_at(const EvalArgs& a, const int4* lds, int idx) {
     return a.sched[idx];
 }
 
-// Entry idx of a clade list cl (this kernel's), staged after the level
-// schedule.
-__device__ inline int4 clade_at(const EvalArgs& a, const int4* lds, const int4* cl, int idx) {
-    if (a.sched_lds) return lds_entry(lds, a.n_sched + idx);
-    return cl[idx];
-}
-
-// Stages the level schedule and the kernel's clade list (cl, n_cl entries;
-// NULL when the kernel has none) in LDS.
-__device__ inline void stage_schedule(const EvalArgs& a, int4* lds, const int4* cl = nullptr) {
+// Stages the level schedule in LDS.
+__device__ inline void stage_schedule(const EvalArgs& a, int4* lds) {
     if (a.sched_lds) {
-        const int n = a.n_sched;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = a.sched[i];
-        if (cl)
-            for (int i = threadIdx.x; i < a.n_cl; i += blockDim.x) lds[n + i] = cl[i];
+        for (int i = threadIdx.x; i < a.n_sched; i += blockDim.x) lds[i] = a.sched[i];
         __syncthreads();
     }
 }

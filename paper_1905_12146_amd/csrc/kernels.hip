@@ -10,11 +10,12 @@
 // A tile is TP consecutive patterns of one rate category (tile = l * n_pb +
 // pattern block), so one node's data for one tile is a single contiguous run.
 //
-// Work decomposition: a workgroup owns one tile and walks the whole tree for
-// it: for small M the clades depth first (one node slot each) and the nodes
-// above them level by level, otherwise every node level by level (nodes of
-// equal height are independent; a barrier separates levels).  Its threads
-// are NS node slots x TP pattern lanes (post_slots / pre_slots).  Tiles
+// Work decomposition: in the level walks a workgroup owns one tile and walks
+// its levels (nodes of equal height are independent; a barrier separates
+// levels) with NS node slots x TP pattern lanes (post_slots / pre_slots).
+// For small M the subtrees below the top (clades) are walked depth first in
+// launches of their own, a wavefront per clade list and four tiles, one per
+// 16-lane row; the level walk then covers only the nodes above them.  Tiles
 // never communicate, so a pass needs no grid-wide synchronisation.
 //
 // Rescaling is per node, pattern and category, by an exact power of two.
@@ -286,7 +287,7 @@ __device__ inline int rslot(int w, int which) { return (w >> (8 * which)) & 0xff
 
 template <typename T>
 __device__ inline T* top_buffer(const EvalArgs& a, int4* lds_sched) {
-    return reinterpret_cast<T*>(lds_sched + (a.sched_lds ? a.n_sched + a.n_cl : 0));
+    return reinterpret_cast<T*>(lds_sched + (a.sched_lds ? a.n_sched : 0));
 }
 
 template <int M, typename T>
@@ -464,19 +465,14 @@ __device__ inline void post_node(const EvalArgs& a, int4 nd, int l, int tile, in
 
 // ---------------------------------------------------------------- clade walks
 //
-// Below the top of the tree each node slot walks whole clades depth first,
-// with no workgroup barrier: entries come in post order (the child with more
-// internal nodes first), so the message of the last finished node is the
-// second child's and stays in registers, and a first child whose sibling is
-// internal parks its message on the slot's LDS stack (at most log2 of the
-// clade size deep).  The pre-order walk takes the same entries backwards and
-// passes q the same way.  Row-uniform control flow throughout: a slot's 16
-// lanes always agree on the entry.
-
-template <int M, typename T>
-__device__ inline T* clade_stack(const EvalArgs& a, T* base, int ns, int ps) {
-    return base + (size_t)ns * a.cl_depth * (M * TP) + ps;
-}
+// Below the top of the tree each clade list is walked depth first with no
+// workgroup barrier (the launches of their own are further below): entries
+// come in post order (the child with more internal nodes first), so the
+// message of the last finished node is the second child's and stays in
+// registers, and a first child whose sibling is internal parks its message
+// on the row's LDS stack (at most log2 of the clade size deep).  The
+// pre-order walk takes the same entries backwards and passes q the same way.
+// Pieces shared by the walks:
 
 template <int M, typename T>
 __device__ inline void stack_push(T* stk, int& sp, const T v[M]) {
@@ -522,16 +518,6 @@ struct ChildAll {
 };
 
 template <int M, typename T>
-__device__ inline void child_load_all(const EvalArgs& a, int c, int l, int tile, int s, int ps, ChildAll<M, T>& r) {
-    const bool tip = c < a.n_tips;
-    const T* src = static_cast<const T*>(a.msg) + (tip ? (size_t)0 : vec_off(a, c, tile, M)) + ps;
-#pragma unroll
-    for (int x = 0; x < M; ++x) r.v[x] = src[x * TP];
-    r.code = a.codes[(size_t)(tip ? c : 0) * a.S_pad + s];
-    r.pe = pmat_of<M, T>(a, c, l)[ps];
-}
-
-template <int M, typename T>
 __device__ inline void child_msg_all(const EvalArgs& a, int c, const ChildAll<M, T>& r,
                                      const unsigned long long* lmask, T out[M]) {
     if (c < a.n_tips) {
@@ -551,73 +537,10 @@ struct PostCladeRaw {
     T pe0, pe1, pk;
 };
 
-template <int M, typename T>
-__device__ inline void post_clade_load(const EvalArgs& a, int4 nd, int l, int s, int ps, PostCladeRaw<M, T>& r) {
-    r.code0 = a.codes[(size_t)(nd.y < a.n_tips ? nd.y : 0) * a.S_pad + s];
-    r.code1 = a.codes[(size_t)(nd.z < a.n_tips ? nd.z : 0) * a.S_pad + s];
-    r.pe0 = pmat_of<M, T>(a, nd.y, l)[ps];
-    r.pe1 = pmat_of<M, T>(a, nd.z, l)[ps];
-    r.pk = pmat_of<M, T>(a, nd.x, l)[ps];
-}
-
 // Copy of the code -> state mask table in LDS (ambiguity codes).
 __device__ inline void stage_masks(const EvalArgs& a, unsigned long long* lmask) {
     for (int i = threadIdx.x; i < 256; i += blockDim.x) lmask[i] = a.masks[i];
     __syncthreads();
-}
-
-template <int M, typename T>
-__device__ inline void post_clades(const EvalArgs& a, const int4* lds, int l, int tile, int s, int ps, int ns,
-                                   T* stk, const unsigned long long* lmask, int& esum) {
-    static_assert(RowMat<M>::value, "clade walks use row-distributed matrices");
-    const int beg = a.cl_post_off[ns], end = a.cl_post_off[ns + 1];
-    if (beg >= end) return;
-    int sp = 0;
-    T acc[M];
-#pragma unroll
-    for (int x = 0; x < M; ++x) acc[x] = T(0);
-    // entries past the end reload the last one, so every iteration issues
-    // the same loads; an entry is read one iteration before its loads
-    auto entry = [&](int i) { return clade_at(a, lds, a.cl_post, min(i, end - 1)); };
-    int4 nd = entry(beg);
-    int4 nn = entry(beg + 1);
-    PostCladeRaw<M, T> cur;
-    post_clade_load<M, T>(a, nd, l, s, ps, cur);
-    for (int i = beg;; ++i) {
-        const int4 n2 = entry(i + 2);
-        PostCladeRaw<M, T> nxt;
-        post_clade_load<M, T>(a, nn, l, s, ps, nxt);
-        T m0[M], m1[M], p[M], mk[M];
-        if (nd.y < a.n_tips) {
-            tip_message<M, T>(cur.code0, cur.pe0, lmask, m0);
-        } else if (nd.z < a.n_tips) {
-#pragma unroll
-            for (int x = 0; x < M; ++x) m0[x] = acc[x];
-        } else {
-            stack_pop<M, T>(stk, sp, m0);
-        }
-        if (nd.z < a.n_tips) {
-            tip_message<M, T>(cur.code1, cur.pe1, lmask, m1);
-        } else {
-#pragma unroll
-            for (int x = 0; x < M; ++x) m1[x] = acc[x];
-        }
-        post_combine<M, T>(a, nd.x, tile, ps, m0, m1, p, esum);
-        row_matvec<M, T>(cur.pk, p, mk);
-        T* out = static_cast<T*>(a.msg) + vec_off(a, nd.x, tile, M) + ps;
-#pragma unroll
-        for (int x = 0; x < M; ++x) out[x * TP] = mk[x];
-        if (nd.w & CL_STACK) {
-            stack_push<M, T>(stk, sp, mk);
-        } else {
-#pragma unroll
-            for (int x = 0; x < M; ++x) acc[x] = mk[x];
-        }
-        if (i + 1 >= end) break;
-        nd = nn;
-        nn = n2;
-        cur = nxt;
-    }
 }
 
 // Level walk of the post-order pass over the schedule's levels (the whole
@@ -688,18 +611,8 @@ __device__ inline void post_body(const EvalArgs& a, int tile, int4* lds_sched) {
     const int l = tile / a.n_pb, pb = tile % a.n_pb;
     const int ps = threadIdx.x % TP, ns = threadIdx.x / TP;
     const int s = pb * TP + ps;
-    stage_schedule(a, lds_sched, a.n_cl ? a.cl_post : nullptr);
+    stage_schedule(a, lds_sched);
     int esum = 0;
-    if constexpr (RowMat<M>::value) {
-        // clades first: the top's lowest level reads the clade roots' messages
-        if (a.n_cl) {
-            __shared__ unsigned long long lmask[256];
-            stage_masks(a, lmask);
-            post_clades<M, T>(a, lds_sched, l, tile, s, ps, ns,
-                              clade_stack<M, T>(a, top_buffer<T>(a, lds_sched), ns, ps), lmask, esum);
-            __syncthreads();
-        }
-    }
     post_levels<M, T, NS>(a, lds_sched, l, tile, s, ps, ns, esum);
     post_root_exponents<NS>(a, l, tile, s, ps, ns, esum);
 }
@@ -1002,16 +915,6 @@ struct PreCladeRaw {
     ChildAll<M, T> c0, c1;
 };
 
-template <int M, typename T>
-__device__ inline void pre_clade_load(const EvalArgs& a, int4 nd, int l, int tile, int s, int ps,
-                                      PreCladeRaw<M, T>& r) {
-    const T* src = static_cast<const T*>(a.qv) + ((nd.w & CL_ROOT) ? vec_off(a, nd.x, tile, M) : (size_t)0) + ps;
-#pragma unroll
-    for (int x = 0; x < M; ++x) r.q[x] = src[x * TP];
-    child_load_all<M, T>(a, nd.y, l, tile, s, ps, r.c0);
-    child_load_all<M, T>(a, nd.z, l, tile, s, ps, r.c1);
-}
-
 template <int M, typename T, bool HESS, bool NH>
 __device__ inline void pre_clade_node(const EvalArgs& a, int4 nd, int l, int tile, int s, int ps, const Coef& cf,
                                       const PreCladeRaw<M, T>& r, const unsigned long long* lmask, T acc[M],
@@ -1055,44 +958,6 @@ __device__ inline void pre_clade_node(const EvalArgs& a, int4 nd, int l, int til
     }
 }
 
-template <int M, typename T, bool HESS, bool NH>
-__device__ inline void pre_clades(const EvalArgs& a, const int4* lds, int l, int tile, int s, int ps, int ns,
-                                  const Coef& cf, T* stk, const unsigned long long* lmask) {
-    static_assert(RowMat<M>::value, "clade walks use row-distributed matrices");
-    const int beg = a.cl_pre_off[ns], end = a.cl_pre_off[ns + 1];
-    const int n = end - beg;
-    if (n <= 0) return;
-    int sp = 0;
-    T acc[M];
-#pragma unroll
-    for (int x = 0; x < M; ++x) acc[x] = T(0);
-    // entry i of the walk is list entry end - 1 - i; entries past the end
-    // reload the last one, so every step issues the same loads
-    // reload the last one, so every step issues the same loads; an entry is
-    // read one step before its loads are issued
-    auto entry = [&](int i) { return clade_at(a, lds, a.cl_pre, end - 1 - min(i, n - 1)); };
-    int4 nd[CLADE_DEPTH];
-    PreCladeRaw<M, T> raw[CLADE_DEPTH];
-#pragma unroll
-    for (int j = 0; j < CLADE_DEPTH; ++j) {
-        nd[j] = entry(j);
-        pre_clade_load<M, T>(a, nd[j], l, tile, s, ps, raw[j]);
-    }
-    int4 ne = entry(CLADE_DEPTH);
-    // only the processing depends on the step being in range: the refills
-    // are unconditional, so the ring's registers carry no merged values
-    for (int i0 = 0; i0 < n; i0 += CLADE_DEPTH) {
-#pragma unroll
-        for (int j = 0; j < CLADE_DEPTH; ++j) {
-            if (i0 + j < n) pre_clade_node<M, T, HESS, NH>(a, nd[j], l, tile, s, ps, cf, raw[j], lmask, acc, stk, sp);
-            const int4 ne2 = entry(i0 + j + CLADE_DEPTH + 1);
-            nd[j] = ne;
-            pre_clade_load<M, T>(a, nd[j], l, tile, s, ps, raw[j]);
-            ne = ne2;
-        }
-    }
-}
-
 // NH: non-homogeneous model (Q of each child's branch from a table); a
 // separate instantiation, so the homogeneous kernel keeps Q in its arguments.
 template <int M, typename T, bool HESS, bool NH>
@@ -1109,7 +974,7 @@ __device__ inline void pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
         // the category-0 tile of each pattern block also forms its logL part
         if (l == 0 && ns == 0) logl_block_part(a, pb, ps, r);
     }
-    stage_schedule(a, lds_sched, a.n_cl ? a.cl_pre : nullptr);
+    stage_schedule(a, lds_sched);
     T* top = top_buffer<T>(a, lds_sched);
     // top region first: each slot issues its next level's loads (children
     // messages of the post-order pass) before the LDS-only barrier; the last
@@ -1180,15 +1045,6 @@ __device__ inline void pre_body(const EvalArgs& a, int tile, int4* lds_sched) {
             }
         }
         __syncthreads();
-    }
-    // clades last: their roots' q were written above; the stack reuses the
-    // top region's LDS
-    if constexpr (RowMat<M>::value) {
-        if (a.n_cl) {
-            __shared__ unsigned long long lmask[256];
-            stage_masks(a, lmask);
-            pre_clades<M, T, HESS, NH>(a, lds_sched, l, tile, s, ps, ns, cf, clade_stack<M, T>(a, top, ns, ps), lmask);
-        }
     }
 }
 
@@ -1610,7 +1466,8 @@ size_t clade_lds_bytes(const EvalArgs& a, int precision) {
 template <int M, typename T>
 static hipError_t post_launch(const EvalArgs& a, hipStream_t st) {
     const int prec = sizeof(T) == 4 ? PG_FP32 : PG_FP64;
-    if (RowMat<M>::value && split_clades(a)) {
+    if (a.n_cl > 0 && !(RowMat<M>::value && split_clades(a))) return hipErrorInvalidValue;
+    if (a.n_cl > 0) {
         constexpr int NQ = post_slots<T>(M) / CW_WAVES;
         post_clade_kernel<M, T><<<cw_groups(a) * NQ, CW_WAVES * 64, cw_lds_bytes(a, sizeof(T)), st>>>(a);
         const EvalArgs t = top_only(a, NQ);
@@ -1636,7 +1493,7 @@ template <int M, typename T, bool HESS, bool NH>
 static void pre_launch_variant(const EvalArgs& a, hipStream_t st) {
     const int prec = sizeof(T) == 4 ? PG_FP32 : PG_FP64;
     const dim3 block(pre_slots<T>(M) * TP);
-    if (RowMat<M>::value && split_clades(a)) {
+    if (a.n_cl > 0) {
         constexpr int NQ = pre_slots<T>(M) / CW_WAVES;
         const EvalArgs t = top_only(a, 0);
         pre_kernel<M, T, HESS, NH><<<a.n_tiles, block, pre_lds_bytes(t, prec), st>>>(t);
@@ -1648,6 +1505,7 @@ static void pre_launch_variant(const EvalArgs& a, hipStream_t st) {
 
 template <int M, typename T>
 static hipError_t pre_launch(const EvalArgs& a, hipStream_t st, bool hess) {
+    if (a.n_cl > 0 && !(RowMat<M>::value && split_clades(a))) return hipErrorInvalidValue;
     if (a.n_models) {
         if (hess) pre_launch_variant<M, T, true, true>(a, st);
         else pre_launch_variant<M, T, false, true>(a, st);
@@ -1715,14 +1573,12 @@ int gsum_total_blocks(const EvalArgs& a) { return gsum_blocks(a.n_branches) + 1;
 
 size_t post_lds_bytes(const EvalArgs& a, int precision) {
     if (precision == PG_SPLIT_BF16) return mfma_post_lds_bytes(a);
-    const size_t es = precision == PG_FP32 ? 4 : 8;
-    return sched_lds_bytes(a) + clade_stack_bytes(a, post_node_slots(a.M, precision), es);
+    return sched_lds_bytes(a);
 }
 size_t pre_lds_bytes(const EvalArgs& a, int precision) {
     if (precision == PG_SPLIT_BF16) return mfma_pre_lds_bytes(a);
     const size_t es = precision == PG_FP32 ? 4 : 8;
-    return sched_lds_bytes(a) +
-           std::max(top_lds_bytes(a, es), clade_stack_bytes(a, pre_node_slots(a.M, precision), es));
+    return sched_lds_bytes(a) + top_lds_bytes(a, es);
 }
 
 template <int M, typename T>

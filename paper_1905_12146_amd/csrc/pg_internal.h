@@ -192,10 +192,7 @@ constexpr int dn_qfrag_elems(int M) { return 2 * dn_nf(M) * 64; }
 
 // Kernel launchers (kernels.hip).  Each returns a hipError_t from the launch.
 bool kernel_supported(int M, int precision);
-inline size_t sched_lds_bytes(const EvalArgs& a) { return a.sched_lds ? sizeof(int4) * (a.n_sched + a.n_cl) : 0; }
-inline size_t clade_stack_bytes(const EvalArgs& a, int slots, size_t elem) {
-    return elem * (size_t)slots * a.cl_depth * a.M * TP;
-}
+inline size_t sched_lds_bytes(const EvalArgs& a) { return a.sched_lds ? sizeof(int4) * a.n_sched : 0; }
 inline size_t top_lds_bytes(const EvalArgs& a, size_t elem) { return elem * (size_t)a.top_nodes * a.M * TP; }
 hipError_t launch_pmat(const EvalArgs& a, int precision, hipStream_t s);
 hipError_t launch_post(const EvalArgs& a, int precision, hipStream_t s);

@@ -290,6 +290,8 @@ int run_group(pg_server* s, std::vector<Item>& items) {
     int pm = 0, tr = 0, gs = 0, cl = 0;
     size_t post_lds = 0, pre_lds = 0, clade_lds = 0;
     for (auto& it : items) {
+        // a plan with clades always takes the clade launches
+        if (it.args.n_cl > 0 && clade_blocks(it.args, s->precision) == 0) return PG_E_DEVICE;
         const EvalArgs top = clade_top_args(it.args, s->precision);
         t_total += it.args.n_branches;
         pm += pmat_blocks(it.args, s->precision);

@@ -109,17 +109,44 @@ struct SiteLik {
     bool nan;
 };
 
+// The categories are read SL_CHUNK at a time, every load of a chunk issued
+// before any is used (one memory round trip per chunk, not per category);
+// the sums still run over l in increasing order.
+constexpr int SL_CHUNK = 4;
+
 __device__ inline SiteLik site_likelihood(const EvalArgs& a, int s) {
     SiteLik r{0.0, INT_MIN, false};
-    for (int l = 0; l < a.K; ++l) {
-        const double L = a.rootL[(size_t)l * a.S_pad + s];
-        if (isnan(L)) r.nan = true;
-        if (L > 0.0) r.emax = max(r.emax, a.rootE[(size_t)l * a.S_pad + s]);
+    for (int l0 = 0; l0 < a.K; l0 += SL_CHUNK) {
+        double L[SL_CHUNK];
+        int E[SL_CHUNK];
+#pragma unroll
+        for (int c = 0; c < SL_CHUNK; ++c) {
+            const size_t at = (size_t)min(l0 + c, a.K - 1) * a.S_pad + s;
+            L[c] = a.rootL[at];
+            E[c] = a.rootE[at];
+        }
+#pragma unroll
+        for (int c = 0; c < SL_CHUNK; ++c) {
+            if (l0 + c >= a.K) break;
+            if (isnan(L[c])) r.nan = true;
+            if (L[c] > 0.0) r.emax = max(r.emax, E[c]);
+        }
     }
     if (r.emax != INT_MIN)
-        for (int l = 0; l < a.K; ++l) {
-            const double L = a.rootL[(size_t)l * a.S_pad + s];
-            if (L > 0.0) r.scaled += a.catw[l] * ldexp(L, a.rootE[(size_t)l * a.S_pad + s] - r.emax);
+        for (int l0 = 0; l0 < a.K; l0 += SL_CHUNK) {
+            double L[SL_CHUNK];
+            int E[SL_CHUNK];
+#pragma unroll
+            for (int c = 0; c < SL_CHUNK; ++c) {
+                const size_t at = (size_t)min(l0 + c, a.K - 1) * a.S_pad + s;
+                L[c] = a.rootL[at];
+                E[c] = a.rootE[at];
+            }
+#pragma unroll
+            for (int c = 0; c < SL_CHUNK; ++c) {
+                if (l0 + c >= a.K) break;
+                if (L[c] > 0.0) r.scaled += a.catw[l0 + c] * ldexp(L[c], E[c] - r.emax);
+            }
         }
     return r;
 }

@@ -403,9 +403,10 @@ __device__ inline void pmat_lds_body(const EvalArgs& a, int block) {
 
 // p~_k of node k from its children's messages, with the exponent
 // bookkeeping (esum, and the stored per-node exponents when kept).
+// p = mi o mj rescaled by the exact power of two 2^-e that brings its
+// largest entry into [1/2, 1); returns e (0 for an all-zero product).
 template <int M, typename T>
-__device__ inline void post_combine(const EvalArgs& a, int k, int tile, int ps, const T mi[M], const T mj[M],
-                                    T p[M], int& esum) {
+__device__ inline int scaled_product(const T mi[M], const T mj[M], T p[M]) {
     T mx = T(0);
 #pragma unroll
     for (int x = 0; x < M; ++x) {
@@ -418,6 +419,13 @@ __device__ inline void post_combine(const EvalArgs& a, int k, int tile, int ps, 
 #pragma unroll
         for (int x = 0; x < M; ++x) p[x] = pow2_scale(p[x], -e);
     }
+    return e;
+}
+
+template <int M, typename T>
+__device__ inline void post_combine(const EvalArgs& a, int k, int tile, int ps, const T mi[M], const T mj[M],
+                                    T p[M], int& esum) {
+    const int e = scaled_product<M, T>(mi, mj, p);
     if (a.expo) {
         // per-node exponents for partial re-evaluation: a pass over some
         // nodes adds the change of each visited node's exponent
@@ -1293,6 +1301,240 @@ pre_clade_batch(const EvalArgs* __restrict__ reqs, const int2* __restrict__ map)
     pre_clade_body<M, T, false, false>(reqs[m.x], m.y, lds_dyn);
 }
 
+// ---------------------------------------------------------------- top levels next to the clade launches
+//
+// With the clade walks in launches of their own, the levels above the clades
+// are a short chain of narrow levels, and every value they read from memory
+// was written by an earlier launch: the clade roots' messages, the tips'
+// codes, the branch matrices and, in the pre-order pass, the post-order
+// messages.  Only the top nodes' own results pass from level to level
+// (messages upwards, q downwards), and those stay in the top region in LDS.
+// So each row issues the loads of all its top nodes at the start and waits
+// for them once; the levels are then separated by LDS-only barriers, and no
+// global store is waited for before the launch ends.  (In the level walk a
+// level's loads wait behind the previous level's stores, which makes every
+// level as long as a memory round trip.)
+//
+// Top node i (schedule order, levels in order) goes to row i % NS.  A level
+// of the top region holds at most NS nodes, so they are on different rows,
+// and a row holds at most TOP_J nodes (the launcher checks both).  The
+// per-lane arithmetic is that of the level walk, so both give the same bits.
+constexpr int TOP_J = 4;
+
+template <int M, typename T>
+struct TopRaw {
+    int4 nd;  // {node, child 0, child 1, region slots}
+    ChildAll<M, T> c0, c1;
+    T pk;  // post order: this lane's entry of the node's own matrix
+};
+
+template <int M>
+__device__ inline CwLane top_lane(const EvalArgs& a, int tile) {
+    CwLane ln;
+    ln.tile = tile;
+    ln.l = tile / a.n_pb;
+    ln.pb = tile % a.n_pb;
+    ln.ps = threadIdx.x % TP;
+    ln.s = ln.pb * TP + ln.ps;
+    ln.vec = (unsigned)(tile * (M * TP) + ln.ps);
+    ln.pe = (unsigned)(ln.l * (M * M) + ln.ps);
+    return ln;
+}
+
+// A child's loads; from_mem = false reads a valid, unused message slot in
+// place of the child's (tips, and region children of the post-order pass,
+// whose messages this launch forms).
+template <int M, typename T>
+__device__ inline void top_child_load(const EvalArgs& a, int c, bool from_mem, const CwLane& ln,
+                                      ChildAll<M, T>& r) {
+    const T* src = node_block<M, T>(a, a.msg, (c >= a.n_tips && from_mem) ? c : a.n_tips) + ln.vec;
+#pragma unroll
+    for (int x = 0; x < M; ++x) r.v[x] = src[x * TP];
+    r.code = code_row(a, c < a.n_tips ? c : 0)[ln.s];
+    r.pe = branch_mats<M, T>(a, c)[ln.pe];
+}
+
+// The loads of top node i; a row without an i-th node loads another node's
+// (valid, unused).
+template <int M, typename T, bool POST>
+__device__ inline void top_load(const EvalArgs& a, int i, const CwLane& ln, TopRaw<M, T>& r) {
+    r.nd = a.sched[min(max(i, 0), a.n_sched - 1)];
+    top_child_load<M, T>(a, r.nd.y, !POST || rslot(r.nd.w, 1) == 0, ln, r.c0);
+    top_child_load<M, T>(a, r.nd.z, !POST || rslot(r.nd.w, 2) == 0, ln, r.c1);
+    r.pk = T(0);
+    if constexpr (POST) r.pk = branch_mats<M, T>(a, r.nd.x == a.root ? 0 : r.nd.x)[ln.pe];
+}
+
+// A row's nodes are taken in order from raw[0]; after each, the rest move
+// down one place (constant indices only: an indexed register array would
+// live in scratch memory).
+template <int M, typename T>
+__device__ inline void top_shift(TopRaw<M, T> (&raw)[TOP_J]) {
+#pragma unroll
+    for (int k = 0; k + 1 < TOP_J; ++k) raw[k] = raw[k + 1];
+}
+
+template <int M, typename T>
+__device__ inline void top_vec_load(const T* top, int slot, int ps, T v[M]) {
+    const T* src = top_vec<M, T>(const_cast<T*>(top), slot, ps);
+#pragma unroll
+    for (int x = 0; x < M; ++x) v[x] = src[x * TP];
+}
+
+template <int M, typename T>
+__device__ inline void post_top_body(const EvalArgs& a, int tile, T* top) {
+    constexpr int NS = post_slots<T>(M);
+    const int row = threadIdx.x / TP;
+    const CwLane ln = top_lane<M>(a, tile);
+    TopRaw<M, T> raw[TOP_J];
+#pragma unroll
+    for (int j = 0; j < TOP_J; ++j) top_load<M, T, true>(a, row + j * NS, ln, raw[j]);
+    // the clade launch's exponent parts of the pattern (row 0 adds them)
+    constexpr int NQ = NS / CW_WAVES;
+    int parts[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        parts[q] = a.cl_esum[((size_t)min(q, a.n_cl_esum - 1) * a.n_tiles + tile) * TP + ln.ps];
+    __shared__ unsigned long long lmask[256];
+    stage_masks(a, lmask);  // its barrier also waits for the loads above
+    int esum = 0, j = 0;
+    for (int h = 0; h < a.n_levels; ++h) {
+        // this row's next node (row + j NS, in raw[0]) lies on level h when it
+        // precedes the next level
+        if (j < TOP_J && row + j * NS < uniform_int(a.level_off, h + 1)) {
+            const TopRaw<M, T>& r = raw[0];
+            const int4 nd = r.nd;
+            T m0[M], m1[M], p[M];
+            if (const int s0 = rslot(nd.w, 1)) top_vec_load<M, T>(top, s0, ln.ps, m0);
+            else child_msg_all<M, T>(a, nd.y, r.c0, lmask, m0);
+            if (const int s1 = rslot(nd.w, 2)) top_vec_load<M, T>(top, s1, ln.ps, m1);
+            else child_msg_all<M, T>(a, nd.z, r.c1, lmask, m1);
+            esum += scaled_product<M, T>(m0, m1, p);
+            if (nd.x != a.root) {
+                T mk[M];
+                row_matvec<M, T>(r.pk, p, mk);
+                T* out = const_cast<T*>(node_block<M, T>(a, a.msg, nd.x)) + ln.vec;
+                T* keep = top_vec<M, T>(top, rslot(nd.w, 0), ln.ps);
+#pragma unroll
+                for (int x = 0; x < M; ++x) {
+                    out[x * TP] = mk[x];
+                    keep[x * TP] = mk[x];
+                }
+            } else {
+                double Lt = 0.0;
+#pragma unroll
+                for (int x = 0; x < M; ++x) Lt = fma(pientry<M>(a, x), (double)p[x], Lt);
+                a.rootL[(size_t)ln.l * a.S_pad + ln.s] = Lt;
+            }
+            top_shift<M, T>(raw);
+            ++j;
+        }
+        lds_barrier();
+    }
+    // the pattern's summed exponent: the rows' sums in row order, then the
+    // clade launch's parts
+    __shared__ int red[NS][TP];
+    red[row][ln.ps] = esum;
+    __syncthreads();
+    if (row == 0) {
+        int tot = 0;
+        for (int i = 0; i < NS; ++i) tot += red[i][ln.ps];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (q < a.n_cl_esum) tot += parts[q];
+        a.rootE[(size_t)ln.l * a.S_pad + ln.s] = tot;
+    }
+}
+
+// q~ of internal child c: to its region slot, or to memory for a clade root
+template <int M, typename T>
+__device__ inline void top_store_q(const EvalArgs& a, int c, int slot, const CwLane& ln, const T qc[M], T* top) {
+    if (slot) {
+        T* d = top_vec<M, T>(top, slot, ln.ps);
+#pragma unroll
+        for (int y = 0; y < M; ++y) d[y * TP] = qc[y];
+    } else {
+        T* d = const_cast<T*>(node_block<M, T>(a, a.qv, c)) + ln.vec;
+#pragma unroll
+        for (int y = 0; y < M; ++y) d[y * TP] = qc[y];
+    }
+}
+
+template <int M, typename T, bool HESS>
+__device__ inline void pre_top_body(const EvalArgs& a, int tile, T* top) {
+    constexpr int NS = pre_slots<T>(M);
+    const int row = threadIdx.x / TP;
+    const CwLane ln = top_lane<M>(a, tile);
+    // the levels from the root down take this row's n nodes in decreasing
+    // order: raw[k] holds node row + (n - 1 - k) NS
+    const int n = row < a.n_sched ? min(TOP_J, (a.n_sched - 1 - row) / NS + 1) : 0;
+    TopRaw<M, T> raw[TOP_J];
+#pragma unroll
+    for (int k = 0; k < TOP_J; ++k) top_load<M, T, false>(a, row + (n - 1 - k) * NS, ln, raw[k]);
+    // rho_{s,l} gamma_l w_s from the per-category root values; the
+    // category-0 tile of each pattern block also forms its logL part
+    Coef cf;
+    {
+        const SiteLik r = site_likelihood(a, ln.s);
+        cf = coef_of(a, ln.l, ln.s, r);
+        if (ln.l == 0 && row == 0) logl_block_part(a, ln.pb, ln.ps, r);
+    }
+    __shared__ unsigned long long lmask[256];
+    stage_masks(a, lmask);
+    int j = n - 1;
+    for (int h = a.n_levels - 1; h >= 0; --h) {
+        if (j >= 0 && row + j * NS >= uniform_int(a.level_off, h)) {
+            const TopRaw<M, T>& r = raw[0];
+            const int4 nd = r.nd;
+            T q[M];
+            if (nd.x == a.root) {
+#pragma unroll
+                for (int x = 0; x < M; ++x) q[x] = T(pientry<M>(a, x));
+            } else {
+                top_vec_load<M, T>(top, rslot(nd.w, 0), ln.ps, q);
+            }
+            T m0[M], m1[M], u0[M], u1[M];
+            child_msg_all<M, T>(a, nd.y, r.c0, lmask, m0);
+            child_msg_all<M, T>(a, nd.z, r.c1, lmask, m1);
+#pragma unroll
+            for (int x = 0; x < M; ++x) {
+                u0[x] = q[x] * m1[x];
+                u1[x] = q[x] * m0[x];
+            }
+            const double rden = node_rden<M, T>(u0, m0);
+            double t0, t1, h0 = 0.0, h1 = 0.0;
+            T q0[M], q1[M];
+            const bool in0 = pre_child_core<M, T, HESS, false>(a, nd.y, ln.l, tile, ln.s, ln.ps, cf, u0, m0, rden,
+                                                               r.c0.pe, t0, h0, q0);
+            if constexpr (!PAIR_TERMS<HESS, false>) store_terms<HESS, T>(a, tile, ln.ps, nd.y, t0, h0);
+            const bool in1 = pre_child_core<M, T, HESS, false>(a, nd.z, ln.l, tile, ln.s, ln.ps, cf, u1, m1, rden,
+                                                               r.c1.pe, t1, h1, q1);
+            if constexpr (!PAIR_TERMS<HESS, false>) store_terms<HESS, T>(a, tile, ln.ps, nd.z, t1, h1);
+            else store_pair_terms<HESS, T>(a, tile, ln.ps, nd, t0, t1, h0, h1);
+            if (in0) top_store_q<M, T>(a, nd.y, rslot(nd.w, 1), ln, q0, top);
+            if (in1) top_store_q<M, T>(a, nd.z, rslot(nd.w, 2), ln, q1, top);
+            top_shift<M, T>(raw);
+            --j;
+        }
+        lds_barrier();
+    }
+}
+
+// One tile per workgroup, as the level walk; two resident workgroups per CU
+// hold every tile of a 500-tile launch.
+template <int M, typename T>
+__global__ void __launch_bounds__(post_slots<T>(M) * TP)
+__attribute__((amdgpu_waves_per_eu(post_slots<T>(M) * TP / 128))) post_top_kernel(EvalArgs a) {
+    extern __shared__ int4 lds_dyn[];
+    post_top_body<M, T>(a, blockIdx.x, reinterpret_cast<T*>(lds_dyn));
+}
+template <int M, typename T, bool HESS>
+__global__ void __launch_bounds__(pre_slots<T>(M) * TP)
+__attribute__((amdgpu_waves_per_eu(pre_slots<T>(M) * TP / 128))) pre_top_kernel(EvalArgs a) {
+    extern __shared__ int4 lds_dyn[];
+    pre_top_body<M, T, HESS>(a, blockIdx.x, reinterpret_cast<T*>(lds_dyn));
+}
+
 // ---------------------------------------------------------------- gradient reduction
 //
 // g_b = sum over tiles of the tile sums, in a fixed order: a block owns
@@ -1463,6 +1705,14 @@ size_t clade_lds_bytes(const EvalArgs& a, int precision) {
     return small_clades(a, precision) ? cw_lds_bytes(a, precision == PG_FP32 ? 4 : 8) : 0;
 }
 
+// The top levels take the prefetching launches when they are one region
+// (every top level narrow enough, at most TOP_J nodes per row) and no
+// per-node exponents of partial re-evaluation are kept.
+static bool top_prefetch(const EvalArgs& t, int ns) {
+    return t.n_cl == 0 && t.top_level == 0 && t.n_sched >= 1 && t.top_nodes == t.n_sched &&
+           t.n_sched <= TOP_J * ns && t.expo == nullptr && !t.expo_delta;
+}
+
 template <int M, typename T>
 static hipError_t post_launch(const EvalArgs& a, hipStream_t st) {
     const int prec = sizeof(T) == 4 ? PG_FP32 : PG_FP64;
@@ -1471,7 +1721,10 @@ static hipError_t post_launch(const EvalArgs& a, hipStream_t st) {
         constexpr int NQ = post_slots<T>(M) / CW_WAVES;
         post_clade_kernel<M, T><<<cw_groups(a) * NQ, CW_WAVES * 64, cw_lds_bytes(a, sizeof(T)), st>>>(a);
         const EvalArgs t = top_only(a, NQ);
-        post_kernel<M, T><<<a.n_tiles, post_slots<T>(M) * TP, post_lds_bytes(t, prec), st>>>(t);
+        if (top_prefetch(t, post_slots<T>(M)) && t.n_cl_esum >= 1 && t.n_cl_esum <= NQ)
+            post_top_kernel<M, T><<<a.n_tiles, post_slots<T>(M) * TP, top_lds_bytes(t, sizeof(T)), st>>>(t);
+        else
+            post_kernel<M, T><<<a.n_tiles, post_slots<T>(M) * TP, post_lds_bytes(t, prec), st>>>(t);
         return hipGetLastError();
     }
     post_kernel<M, T><<<a.n_tiles, post_slots<T>(M) * TP, post_lds_bytes(a, prec), st>>>(a);
@@ -1496,7 +1749,10 @@ static void pre_launch_variant(const EvalArgs& a, hipStream_t st) {
     if (a.n_cl > 0) {
         constexpr int NQ = pre_slots<T>(M) / CW_WAVES;
         const EvalArgs t = top_only(a, 0);
-        pre_kernel<M, T, HESS, NH><<<a.n_tiles, block, pre_lds_bytes(t, prec), st>>>(t);
+        if (!NH && top_prefetch(t, pre_slots<T>(M)))
+            pre_top_kernel<M, T, HESS><<<a.n_tiles, block, top_lds_bytes(t, sizeof(T)), st>>>(t);
+        else
+            pre_kernel<M, T, HESS, NH><<<a.n_tiles, block, pre_lds_bytes(t, prec), st>>>(t);
         pre_clade_kernel<M, T, HESS, NH><<<cw_groups(a) * NQ, CW_WAVES * 64, cw_lds_bytes(a, sizeof(T)), st>>>(a);
         return;
     }

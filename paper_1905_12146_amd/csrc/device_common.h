@@ -127,9 +127,10 @@ __device__ inline SiteLik site_likelihood(const EvalArgs& a, int s) {
         }
 #pragma unroll
         for (int c = 0; c < SL_CHUNK; ++c) {
-            if (l0 + c >= a.K) break;
-            if (isnan(L[c])) r.nan = true;
-            if (L[c] > 0.0) r.emax = max(r.emax, E[c]);
+            if (l0 + c < a.K) {
+                if (isnan(L[c])) r.nan = true;
+                if (L[c] > 0.0) r.emax = max(r.emax, E[c]);
+            }
         }
     }
     if (r.emax != INT_MIN)
@@ -144,8 +145,7 @@ __device__ inline SiteLik site_likelihood(const EvalArgs& a, int s) {
             }
 #pragma unroll
             for (int c = 0; c < SL_CHUNK; ++c) {
-                if (l0 + c >= a.K) break;
-                if (L[c] > 0.0) r.scaled += a.catw[l0 + c] * ldexp(L[c], E[c] - r.emax);
+                if (l0 + c < a.K && L[c] > 0.0) r.scaled += a.catw[l0 + c] * ldexp(L[c], E[c] - r.emax);
             }
         }
     return r;
@@ -202,6 +202,65 @@ __device__ inline Coef coef_of(const EvalArgs& a, int l, int s, const SiteLik& r
         cf.nw = rho * a.rates[l];
         cf.g = a.weights[s] * cf.nw;
         cf.h = cf.g * a.rates[l];
+    }
+    return cf;
+}
+
+
+// The values site_likelihood and coef_of read for pattern s and category l,
+// loaded together so that one memory round trip covers them (the first
+// SL_CHUNK categories; site_coef falls back to the two functions above for
+// more categories).
+struct SiteVals {
+    double L[SL_CHUNK], cw[SL_CHUNK];
+    int E[SL_CHUNK];
+    double Ll, cwl, w, rate;  // category l's root value and weight, w_s, gamma_l
+    int El;
+};
+
+__device__ inline void site_vals_load(const EvalArgs& a, int l, int s, SiteVals& v) {
+#pragma unroll
+    for (int c = 0; c < SL_CHUNK; ++c) {
+        const int lc = min(c, a.K - 1);
+        const size_t at = (size_t)lc * a.S_pad + s;
+        v.L[c] = a.rootL[at];
+        v.E[c] = a.rootE[at];
+        v.cw[c] = a.catw[lc];
+    }
+    const size_t at = (size_t)l * a.S_pad + s;
+    v.Ll = a.rootL[at];
+    v.El = a.rootE[at];
+    v.cwl = a.catw[l];
+    v.w = a.weights[s];
+    v.rate = a.rates[l];
+}
+
+// site_likelihood and coef_of of category l from the loaded values: the same
+// operations in the same order, so the same bits.
+__device__ inline Coef site_coef(const EvalArgs& a, int l, int s, const SiteVals& v, SiteLik& r) {
+    if (a.K > SL_CHUNK) {
+        r = site_likelihood(a, s);
+        return coef_of(a, l, s, r);
+    }
+    r = SiteLik{0.0, INT_MIN, false};
+#pragma unroll
+    for (int c = 0; c < SL_CHUNK; ++c) {
+        if (c < a.K) {
+            if (isnan(v.L[c])) r.nan = true;
+            if (v.L[c] > 0.0) r.emax = max(r.emax, v.E[c]);
+        }
+    }
+    if (r.emax != INT_MIN)
+#pragma unroll
+        for (int c = 0; c < SL_CHUNK; ++c) {
+            if (c < a.K && v.L[c] > 0.0) r.scaled += v.cw[c] * ldexp(v.L[c], v.E[c] - r.emax);
+        }
+    Coef cf{0.0, 0.0, 0.0};
+    if (!r.nan && r.scaled > 0.0 && v.Ll > 0.0) {
+        const double rho = v.cwl * ldexp(v.Ll, v.El - r.emax) / r.scaled;
+        cf.nw = rho * v.rate;
+        cf.g = v.w * cf.nw;
+        cf.h = cf.g * v.rate;
     }
     return cf;
 }

@@ -550,6 +550,13 @@ __device__ inline void stage_masks(const EvalArgs& a, unsigned long long* lmask)
     for (int i = threadIdx.x; i < 256; i += blockDim.x) lmask[i] = a.masks[i];
     __syncthreads();
 }
+// The same copy in two steps, for blocks of at least 256 threads: the load
+// is issued early with the block's other loads, the store after them (the
+// caller's barrier publishes the table).
+__device__ inline unsigned long long mask_load(const EvalArgs& a) { return a.masks[min((int)threadIdx.x, 255)]; }
+__device__ inline void mask_store(unsigned long long* lmask, unsigned long long v) {
+    if (threadIdx.x < 256) lmask[threadIdx.x] = v;
+}
 
 // Level walk of the post-order pass over the schedule's levels (the whole
 // tree, or the top above the clades): node slot ns of NS takes every NS-th
@@ -1260,9 +1267,15 @@ __device__ inline void pre_clade_body(const EvalArgs& a, int block, int4* lds_dy
     const int group = block / NQ, q = block % NQ;
     const int wave = threadIdx.x / 64;
     const CwLane ln = cw_lane<M>(a, group);
-    const Coef cf = coef_of(a, ln.l, ln.s, site_likelihood(a, ln.s));
+    static_assert(CW_WAVES * 64 >= 256, "one mask per thread");
+    SiteVals sv;
+    site_vals_load(a, ln.l, ln.s, sv);
+    const unsigned long long mv = mask_load(a);
+    SiteLik r;
+    const Coef cf = site_coef(a, ln.l, ln.s, sv, r);
     __shared__ unsigned long long lmask[256];
-    stage_masks(a, lmask);
+    mask_store(lmask, mv);
+    __syncthreads();
     pre_clades_u<M, T, HESS, NH>(a, __builtin_amdgcn_readfirstlane(q * CW_WAVES + wave), ln, cf,
                                  cw_stack<M, T>(a, reinterpret_cast<T*>(lds_dyn)), lmask);
 }
@@ -1467,6 +1480,10 @@ __device__ inline void pre_top_body(const EvalArgs& a, int tile, T* top) {
     const CwLane ln = top_lane<M>(a, tile);
     // the levels from the root down take this row's n nodes in decreasing
     // order: raw[k] holds node row + (n - 1 - k) NS
+    static_assert(NS * TP >= 256, "one mask per thread");
+    SiteVals sv;
+    site_vals_load(a, ln.l, ln.s, sv);
+    const unsigned long long mv = mask_load(a);
     const int n = row < a.n_sched ? min(TOP_J, (a.n_sched - 1 - row) / NS + 1) : 0;
     TopRaw<M, T> raw[TOP_J];
 #pragma unroll
@@ -1475,12 +1492,13 @@ __device__ inline void pre_top_body(const EvalArgs& a, int tile, T* top) {
     // category-0 tile of each pattern block also forms its logL part
     Coef cf;
     {
-        const SiteLik r = site_likelihood(a, ln.s);
-        cf = coef_of(a, ln.l, ln.s, r);
+        SiteLik r;
+        cf = site_coef(a, ln.l, ln.s, sv, r);
         if (ln.l == 0 && row == 0) logl_block_part(a, ln.pb, ln.ps, r);
     }
     __shared__ unsigned long long lmask[256];
-    stage_masks(a, lmask);
+    mask_store(lmask, mv);
+    __syncthreads();
     int j = n - 1;
     for (int h = a.n_levels - 1; h >= 0; --h) {
         if (j >= 0 && row + j * NS >= uniform_int(a.level_off, h)) {

@@ -1332,7 +1332,6 @@ pre_clade_batch(const EvalArgs* __restrict__ reqs, const int2* __restrict__ map)
 // of the top region holds at most NS nodes, so they are on different rows,
 // and a row holds at most TOP_J nodes (the launcher checks both).  The
 // per-lane arithmetic is that of the level walk, so both give the same bits.
-constexpr int TOP_J = 4;
 
 template <int M, typename T>
 struct TopRaw {

@@ -43,6 +43,9 @@ constexpr int SCHED_LDS_MAX = 32768;
 // level it admits (one node per node slot).
 constexpr int TOP_LDS_MAX = 32768;
 constexpr int TOP_LEVEL_MAX_NODES = 16;
+// Top nodes per node slot of the top-level launches next to the clade
+// launches (node i of the top goes to slot i % slots).
+constexpr int TOP_J = 4;
 
 // A schedule entry; the same layout as the device's int4.
 struct Ent {

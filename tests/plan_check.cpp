@@ -14,7 +14,8 @@
 // code, the matrix entries, the q of a clade root), every LDS stack and top
 // region slot, and the data flow (a message or q vector is read only after
 // the walk that writes it).  It also checks that every internal node is
-// scheduled exactly once in each pass, and the dirty-path schedules of
+// scheduled exactly once in each pass, the slot assignment of the top-level
+// launches next to the clade launches, and the dirty-path schedules of
 // partial re-evaluation for random sets of changed branches.
 //
 // Exit status 0 when every check passes; otherwise the first failure is
@@ -33,6 +34,7 @@ using namespace pg;
 namespace {
 
 int g_checks = 0;
+int g_top_plans = 0;  // plans replayed by check_top_launches
 
 #define CHECK(cond, ...)                                                     \
     do {                                                                     \
@@ -345,6 +347,119 @@ struct Walk {
     }
 };
 
+// The top-level launches next to the clade launches (post_top_kernel,
+// pre_top_kernel): node i of the top goes to slot i % ns, each slot loads
+// its TOP_J nodes (clamped indices) at the start, then takes them level by
+// level.  Replays, for every slot, the loads (entries, message blocks, tip
+// code rows, matrix entries), the level on which each node is taken, and the
+// LDS region slots read and written, and checks that every top node is taken
+// exactly once in each pass.  Only plans the launcher sends there.
+void check_top_launches(const Tree& t, const TraversalPlan& pl, int ns) {
+    if (!(pl.n_cl > 0 && pl.top_level == 0 && pl.n_top >= 1 && pl.top_nodes == pl.n_top &&
+          pl.n_top <= TOP_J * ns))
+        return;
+    ++g_top_plans;
+    const int N = t.N, root = 2 * N - 2, H = (int)pl.level_off.size() - 1;
+    const Bounds bd{N, 2 * N - 2, N - 1};
+    std::vector<char> in_top(2 * N - 1, 0);
+    for (int i = 0; i < pl.n_top; ++i) in_top[pl.sched[i].x] = 1;
+    for (int h = 0; h < H; ++h)
+        CHECK(pl.level_off[h + 1] - pl.level_off[h] <= ns, "top level %d wider than %d slots", h, ns);
+    auto slot_of = [&](int w, int which) {
+        const int sl = (w >> (8 * which)) & 0xff;
+        CHECK(sl >= 0 && sl <= pl.top_nodes, "top region slot %d of %d", sl, pl.top_nodes);
+        return sl;
+    };
+    auto entry = [&](int i) -> const Ent& {
+        const int c = std::min(std::max(i, 0), pl.n_top - 1);
+        return pl.sched[c];
+    };
+    auto child_loads = [&](int c, bool msg_from_mem, const char* what) {
+        CHECK(c >= 0 && c < 2 * N - 1 && c != root, "%s: child %d", what, c);
+        bd.msg_block((c >= N && msg_from_mem) ? c : N, what);
+        bd.code_row(c < N ? c : 0, what);
+        bd.pmat(c, what);
+    };
+    // post order: levels upwards, messages of region nodes through LDS
+    {
+        std::vector<int> taken(pl.n_top, 0), lds_level(pl.top_nodes + 1, -1);
+        for (int row = 0; row < ns; ++row) {
+            for (int j = 0; j < TOP_J; ++j) {
+                const Ent& e = entry(row + j * ns);
+                for (int k = 1; k <= 2; ++k) {
+                    const int c = k == 1 ? e.y : e.z;
+                    const int sl = slot_of(e.w, k);
+                    if (c >= N && sl == 0) CHECK(!in_top[c], "post top: top child %d of %d outside the region", c, e.x);
+                    child_loads(c, sl == 0, "post top child");
+                }
+                bd.pmat(e.x == root ? 0 : e.x, "post top own matrix");
+            }
+        }
+        // levels in order; within a level the slots run concurrently, so a
+        // region slot written on level h is readable from level h + 1 on
+        std::vector<int> next(ns, 0);
+        for (int h = 0; h < H; ++h) {
+            for (int row = 0; row < ns; ++row) {
+                const int i = row + next[row] * ns;
+                if (!(next[row] < TOP_J && i < pl.level_off[h + 1])) continue;
+                CHECK(i >= pl.level_off[h], "post top: slot %d node %d taken on level %d", row, i, h);
+                const Ent& e = pl.sched[i];
+                ++taken[i];
+                for (int k = 1; k <= 2; ++k)
+                    if (const int sl = slot_of(e.w, k))
+                        CHECK(lds_level[sl] >= 0 && lds_level[sl] < h, "post top: region slot %d read early", sl);
+                if (e.x != root) {
+                    const int sl = slot_of(e.w, 0);
+                    CHECK(sl >= 1 && lds_level[sl] < 0, "post top: region slot %d of node %d", sl, e.x);
+                    lds_level[sl] = h;
+                }
+                ++next[row];
+            }
+        }
+        for (int i = 0; i < pl.n_top; ++i) CHECK(taken[i] == 1, "post top: node %d taken %d times", i, taken[i]);
+    }
+    // pre order: levels downwards, q of region nodes through LDS
+    {
+        std::vector<int> taken(pl.n_top, 0), lds_level(pl.top_nodes + 1, -1), cnt(ns, 0);
+        for (int row = 0; row < ns; ++row) {
+            const int n = row < pl.n_top ? std::min(TOP_J, (pl.n_top - 1 - row) / ns + 1) : 0;
+            cnt[row] = n;
+            for (int k = 0; k < TOP_J; ++k) {
+                const Ent& e = entry(row + (n - 1 - k) * ns);
+                child_loads(e.y, true, "pre top child");
+                child_loads(e.z, true, "pre top child");
+            }
+        }
+        for (int h = H - 1; h >= 0; --h) {
+            for (int row = 0; row < ns; ++row) {
+                const int j = cnt[row] - 1;
+                if (!(j >= 0 && row + j * ns >= pl.level_off[h])) continue;
+                const int i = row + j * ns;
+                CHECK(i < pl.level_off[h + 1], "pre top: slot %d node %d taken on level %d", row, i, h);
+                const Ent& e = pl.sched[i];
+                ++taken[i];
+                if (e.x != root) {
+                    const int sl = slot_of(e.w, 0);
+                    CHECK(sl >= 1 && lds_level[sl] > h, "pre top: q of node %d (slot %d) read early", e.x, sl);
+                }
+                for (int k = 1; k <= 2; ++k) {
+                    const int c = k == 1 ? e.y : e.z;
+                    if (c < N) continue;
+                    if (const int sl = slot_of(e.w, k)) {
+                        CHECK(lds_level[sl] < 0, "pre top: region slot %d written twice", sl);
+                        lds_level[sl] = h;
+                    } else {
+                        bd.msg_block(c, "pre top q of a clade root");
+                        CHECK(!in_top[c], "pre top: top child %d outside the region", c);
+                    }
+                }
+                --cnt[row];
+            }
+        }
+        for (int i = 0; i < pl.n_top; ++i) CHECK(taken[i] == 1, "pre top: node %d taken %d times", i, taken[i]);
+    }
+}
+
 void check_plan(const Tree& t, const PlanParams& pp) {
     TraversalPlan pl;
     plan_traversal(t.N, t.parent.data(), t.ch.data(), t.lv, pp, pl);
@@ -370,6 +485,7 @@ void check_plan(const Tree& t, const PlanParams& pp) {
     Walk w(t, pl, pp);
     w.post();
     w.pre();
+    if (pp.ns_post == pp.ns_pre) check_top_launches(t, pl, pp.ns_pre);
 }
 
 void check_updates(const Tree& t, std::mt19937_64& rng) {
@@ -499,6 +615,7 @@ int main(int argc, char** argv) {
             for (int n_pb : {1, 2, 3, 125, 313}) check_clade_launch(ns, K, n_pb);
     std::mt19937_64 rng(12146 + t.N);
     check_updates(t, rng);
-    std::printf("plan_check N=%d: %d checks passed\n", t.N, g_checks);
+    std::printf("plan_check N=%d: %d checks passed (%d plans through the top-level launches)\n", t.N, g_checks,
+                g_top_plans);
     return 0;
 }

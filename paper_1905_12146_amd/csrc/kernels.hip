@@ -1551,6 +1551,22 @@ __attribute__((amdgpu_waves_per_eu(pre_slots<T>(M) * TP / 128))) pre_top_kernel(
     extern __shared__ int4 lds_dyn[];
     pre_top_body<M, T, HESS>(a, blockIdx.x, reinterpret_cast<T*>(lds_dyn));
 }
+template <int M, typename T>
+__global__ void __launch_bounds__(post_slots<T>(M) * TP)
+__attribute__((amdgpu_waves_per_eu(post_slots<T>(M) * TP / 128)))
+post_top_batch(const EvalArgs* __restrict__ reqs, const int2* __restrict__ map) {
+    extern __shared__ int4 lds_dyn[];
+    const int2 m = map[blockIdx.x];
+    post_top_body<M, T>(reqs[m.x], m.y, reinterpret_cast<T*>(lds_dyn));
+}
+template <int M, typename T>
+__global__ void __launch_bounds__(pre_slots<T>(M) * TP)
+__attribute__((amdgpu_waves_per_eu(pre_slots<T>(M) * TP / 128)))
+pre_top_batch(const EvalArgs* __restrict__ reqs, const int2* __restrict__ map) {
+    extern __shared__ int4 lds_dyn[];
+    const int2 m = map[blockIdx.x];
+    pre_top_body<M, T, false>(reqs[m.x], m.y, reinterpret_cast<T*>(lds_dyn));
+}
 
 // ---------------------------------------------------------------- gradient reduction
 //
@@ -1730,6 +1746,15 @@ static bool top_prefetch(const EvalArgs& t, int ns) {
            t.n_sched <= TOP_J * ns && t.expo == nullptr && !t.expo_delta;
 }
 
+// Whether a request's top-level launch arguments (clade_top_args) take the
+// top-level launches above in a batch, and their dynamic LDS.
+bool top_launch_ok(const EvalArgs& t, int precision) {
+    if (!(t.M == 4 && (precision == PG_FP64 || precision == PG_FP32))) return false;
+    const int ns = precision == PG_FP32 ? post_slots<float>(4) : post_slots<double>(4);
+    return top_prefetch(t, ns) && t.n_cl_esum >= 1 && t.n_cl_esum <= ns / CW_WAVES && t.n_models == 0;
+}
+size_t top_launch_lds(const EvalArgs& t, int precision) { return top_lds_bytes(t, precision == PG_FP32 ? 4 : 8); }
+
 template <int M, typename T>
 static hipError_t post_launch(const EvalArgs& a, hipStream_t st) {
     const int prec = sizeof(T) == 4 ? PG_FP32 : PG_FP64;
@@ -1865,8 +1890,13 @@ static hipError_t batch_launch(const BatchLaunch& b, hipStream_t st) {
     const EvalArgs* top = b.reqs_top ? b.reqs_top : b.reqs;
     if (b.clade_blocks > 0)
         post_clade_batch<M, T><<<b.clade_blocks, CW_WAVES * 64, b.clade_lds, st>>>(b.reqs, b.clade_map);
-    post_batch<M, T><<<b.trav_blocks, post_slots<T>(M) * TP, b.post_lds, st>>>(top, b.trav_map);
-    pre_batch<M, T><<<b.trav_blocks, pre_slots<T>(M) * TP, b.pre_lds, st>>>(top, b.trav_map);
+    if (b.top_kernels) {
+        post_top_batch<M, T><<<b.trav_blocks, post_slots<T>(M) * TP, b.top_lds, st>>>(top, b.trav_map);
+        pre_top_batch<M, T><<<b.trav_blocks, pre_slots<T>(M) * TP, b.top_lds, st>>>(top, b.trav_map);
+    } else {
+        post_batch<M, T><<<b.trav_blocks, post_slots<T>(M) * TP, b.post_lds, st>>>(top, b.trav_map);
+        pre_batch<M, T><<<b.trav_blocks, pre_slots<T>(M) * TP, b.pre_lds, st>>>(top, b.trav_map);
+    }
     if (b.clade_blocks > 0)
         pre_clade_batch<M, T><<<b.clade_blocks, CW_WAVES * 64, b.clade_lds, st>>>(b.reqs, b.clade_map);
     gsum_batch<<<b.gsum_blocks, GS_THREADS, 0, st>>>(b.reqs, b.gsum_map);

@@ -223,12 +223,16 @@ struct BatchLaunch {
     const int2* clade_map;     // {request, block} of the clade launches
     int pmat_blocks, trav_blocks, gsum_blocks, clade_blocks;
     size_t post_lds, pre_lds, clade_lds;
+    int top_kernels;   // 1: every request's top levels take the top-level launches (top_launch_ok)
+    size_t top_lds;    // their dynamic LDS (largest top_launch_lds)
 };
 // Separate clade launches of small-M requests: their blocks (0: none), the
 // arguments of their top-level (traversal) launches, their dynamic LDS.
 int clade_blocks(const EvalArgs& a, int precision);
 EvalArgs clade_top_args(const EvalArgs& a, int precision);
 size_t clade_lds_bytes(const EvalArgs& a, int precision);
+bool top_launch_ok(const EvalArgs& top, int precision);
+size_t top_launch_lds(const EvalArgs& top, int precision);
 int pmat_blocks(const EvalArgs& a, int precision);
 int traversal_blocks(const EvalArgs& a);
 int gsum_total_blocks(const EvalArgs& a);

@@ -288,7 +288,8 @@ int run_group(pg_server* s, std::vector<Item>& items) {
     // [pmat map][trav map][gsum map][clade map]
     size_t t_total = 0;
     int pm = 0, tr = 0, gs = 0, cl = 0;
-    size_t post_lds = 0, pre_lds = 0, clade_lds = 0;
+    size_t post_lds = 0, pre_lds = 0, clade_lds = 0, top_lds = 0;
+    bool top_kernels = true;
     for (auto& it : items) {
         // a plan with clades always takes the clade launches
         if (it.args.n_cl > 0 && clade_blocks(it.args, s->precision) == 0) return PG_E_DEVICE;
@@ -301,6 +302,9 @@ int run_group(pg_server* s, std::vector<Item>& items) {
         post_lds = std::max(post_lds, post_lds_bytes(top, s->precision));
         pre_lds = std::max(pre_lds, pre_lds_bytes(top, s->precision));
         clade_lds = std::max(clade_lds, clade_lds_bytes(it.args, s->precision));
+        // the top-level launches serve the batch when they serve every request
+        top_kernels = top_kernels && it.args.n_cl > 0 && top_launch_ok(top, s->precision);
+        top_lds = std::max(top_lds, top_launch_lds(top, s->precision));
     }
     const size_t off_t = 0;
     const size_t off_args = align16(off_t + sizeof(double) * t_total);
@@ -364,6 +368,8 @@ int run_group(pg_server* s, std::vector<Item>& items) {
     bl.clade_blocks = cl;
     bl.post_lds = post_lds;
     bl.pre_lds = pre_lds;
+    bl.top_kernels = top_kernels ? 1 : 0;
+    bl.top_lds = top_lds;
     bl.clade_lds = clade_lds;
     if ((e = launch_batch(bl, s->stream)) != hipSuccess) return PG_E_DEVICE;
     if ((e = hipMemcpyAsync(s->h_out, s->d_out, out_bytes, hipMemcpyDeviceToHost, s->stream)) != hipSuccess)
